@@ -1,0 +1,233 @@
+"""Benchmark of the FX correlator hot path on one MI355X.
+
+A step is one ~1 s block of the 16-bit one-GPU share (76 stations x 2 polarisations, 64
+subbands, complex int16 samples, 16-tap PPF -> 64 channels, 3072 channel samples, FP16-split
+MFMA X stage) through the whole chain: F stage (unpack, FIR, FFT, fine delay, bandpass,
+transpose, FP16 hi/lo split) then X stage.  Inputs are synthetic and already resident in HBM
+when timing starts.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--fp32-steps F]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "correlator TeraMACs/s and real-time factor at 76 stations; p99 block latency"
+HBM_PEAK_GBS = 8000.0
+FP16_MFMA_PEAK_TFLOPS = 2516.6       # dense fp16 MFMA, 256 CU x 2.4 GHz x 4096 flop/clk
+INT8_MFMA_PEAK_TOPS = 5033.2
+FP32_VALU_PEAK_TFLOPS = 157.3        # published vector FP32 (dual-issue/packed)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="int16_share", choices=["int16_share", "int8_full", "plain_fx"])
+    ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 form (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-subbands", type=int, default=1, help="subbands in the oracle sample")
+    return ap.parse_args()
+
+
+def make_input(w, torch, device):
+    """Synthetic block on the device, generated on the host one subband group at a time."""
+    x = torch.empty((w.S, 2, w.SB, w.N, 2), dtype={1: torch.int8, 2: torch.int16, 3: torch.float32}[w.sample_type],
+                    device=device)
+    step = 8
+    for sb0 in range(0, w.SB, step):
+        sbs = list(range(sb0, min(w.SB, sb0 + step)))
+        part = w.block(0, subbands=sbs)
+        x[:, :, sb0:sb0 + len(sbs)].copy_(torch.from_numpy(part))
+    return x
+
+
+def time_steps(torch, plan, x, delays, steps, warmup):
+    """F then X per step on the current stream, HIP events around each kernel."""
+    chan = plan.empty_chan()
+    vis = plan.empty_vis()
+    for _ in range(warmup):
+        plan.channelize(x, delays, out=chan)
+        plan.correlate_channelized(chan, out=vis)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        plan.channelize(x, delays, out=chan)
+        ev[k][1].record()
+        plan.correlate_channelized(chan, out=vis)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    f_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    x_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    return wall, f_ms, x_ms, vis
+
+
+def block_latency(torch, plan, x, delays, n):
+    """Submit one block, wait for it; host-side enqueue-to-completion time (ms)."""
+    vis = plan.empty_vis()
+    out = []
+    for _ in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.correlate(x, delays, out=vis)
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) * 1e3)
+    return np.array(out)
+
+
+def cpu_baseline(w, n_sub):
+    """The FP64 oracle on n_sub subbands of the same workload, on this host's cores."""
+    import oracle
+    from paper_1801_04834_amd import synth
+    try:
+        import threadpoolctl
+        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    sbs = list(range(n_sub))
+    x = synth.to_complex(w.block(0, subbands=sbs))
+    hist = np.zeros((w.S, 2, n_sub, 960), np.complex128)
+    mode = {synth.X_FP32: "fp32", synth.X_FP16_SPLIT: "fp16_split", synth.X_INT8: "int8"}[w.x_mode]
+    t0 = time.perf_counter()
+    oracle.fx_block(x, hist, w.fir(), w.bandpass(), w.subband_freqs()[:n_sub], synth.SAMPLE_RATE_HZ,
+                    w.delays(0), 64, 16, mode=mode, gain=w.gain(), return_channelised=False)
+    dt = time.perf_counter() - t0
+    cmacs = w.n_baselines * 4 * n_sub * w.C * w.n_c
+    return {"value": cmacs / dt / 1e12, "unit": "TeraMAC/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_sub} of {w.SB} subbands of the same block (all {w.S} stations, N={w.N}); "
+                      f"{dt:.2f} s per sample, real-time factor {w.N / 195312.5 * n_sub / w.SB / dt:.4f} "
+                      f"for the whole block",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the FX chain shards over "
+              "subbands with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1801_04834_amd import binding, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = synth.workload(args.workload)
+    log(f"bench: workload {w.name} S={w.S} SB={w.SB} N={w.N} mode={w.x_mode}; generating input")
+    t0 = time.perf_counter()
+    x = make_input(w, torch, dev)
+    delays = w.delays(0)
+    torch.cuda.synchronize()
+    log(f"bench: input {x.numel() * x.element_size() / 1e9:.2f} GB resident ({time.perf_counter() - t0:.1f} s)")
+
+    plan = binding.plan_for(w)
+    info = plan.info
+    cmacs = info["useful_cmacs"]
+    block_s = w.N / synth.SAMPLE_RATE_HZ
+    wall, f_ms, x_ms, vis = time_steps(torch, plan, x, delays, args.steps, args.warmup)
+    log(f"bench: {args.steps} steps, wall {wall * 1e3:.3f} ms/step, F {np.mean(f_ms):.3f} ms, X {np.mean(x_ms):.3f} ms")
+    step_ms = wall * 1e3
+    lat = block_latency(torch, plan, x, delays, max(args.steps, 20))
+    log(f"bench: block latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    # algorithmic work per launch
+    samples = w.M * w.SB * w.N
+    sample_b = {synth.CI8: 2, synth.CI16: 4, synth.CF32: 8}[w.sample_type]
+    chan_b = {synth.X_FP32: 8, synth.X_FP16_SPLIT: 8, synth.X_INT8: 2}[w.x_mode]
+    f_bytes = samples * (sample_b + chan_b)
+    f_ms_avg = float(np.mean(f_ms))
+    x_ms_avg = float(np.mean(x_ms))
+    f_gbs = f_bytes / (f_ms_avg * 1e-3) / 1e9
+    x_tmacs = cmacs / (x_ms_avg * 1e-3) / 1e12
+    if w.x_mode == synth.X_FP16_SPLIT:
+        x_mfma_tflops = cmacs * 8 * 3 / (x_ms_avg * 1e-3) / 1e12
+        x_peak, x_unit = FP16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+    elif w.x_mode == synth.X_INT8:
+        x_mfma_tflops = cmacs * 8 / (x_ms_avg * 1e-3) / 1e12
+        x_peak, x_unit = INT8_MFMA_PEAK_TOPS, "TOP/s"
+    else:
+        x_mfma_tflops = cmacs * 8 / (x_ms_avg * 1e-3) / 1e12
+        x_peak, x_unit = FP32_VALU_PEAK_TFLOPS, "TFLOP/s"
+    x_bytes = w.SB * w.C * w.M * w.n_c * chan_b
+    f_roof = {"bound": "hbm", "achieved": round(f_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(f_gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "fstage",
+              "ms": round(f_ms_avg, 4), "algorithmic_bytes": f_bytes}
+    x_roof = {"bound": "mfma" if w.x_mode != synth.X_FP32 else "alu", "achieved": round(x_mfma_tflops, 1),
+              "peak": x_peak, "unit": x_unit, "frac": round(x_mfma_tflops / x_peak, 4), "traffic": None,
+              "kernel": "xstage", "ms": round(x_ms_avg, 4),
+              "operand_gbs": round(x_bytes / (x_ms_avg * 1e-3) / 1e9, 1)}
+    dominant = f_roof if f_ms_avg >= x_ms_avg else x_roof
+    other = x_roof if dominant is f_roof else f_roof
+
+    fp32 = None
+    if args.fp32_steps > 0 and w.x_mode != synth.X_FP32:
+        del vis
+        plan32 = binding.plan_for(w, x_mode=synth.X_FP32)
+        wall32, f32, x32, v32 = time_steps(torch, plan32, x, delays, args.fp32_steps, 1)
+        fp32 = {"ms_per_step": round(wall32 * 1e3, 3), "x_ms": round(float(np.mean(x32)), 3),
+                "f_ms": round(float(np.mean(f32)), 3),
+                "x_tmacs": round(cmacs / (float(np.mean(x32)) * 1e-3) / 1e12, 3),
+                "real_time_factor": round(block_s / wall32, 2)}
+        log(f"bench: plain FP32 form {wall32 * 1e3:.3f} ms/step (X {np.mean(x32):.3f} ms)")
+        del v32
+        plan32.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"bench: oracle on {args.cpu_subbands} subband(s) for the CPU baseline")
+        cpu = cpu_baseline(w, args.cpu_subbands)
+        log(f"bench: oracle {cpu['seconds']:.2f} s -> {cpu['value']:.5f} TeraMAC/s")
+
+    value = cmacs / (step_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "TeraMAC/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {synth.X_FP16_SPLIT: "fp16x3-split/fp32-acc", synth.X_INT8: "int8/int32-acc",
+                  synth.X_FP32: "fp32"}[w.x_mode],
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.S} stations x 2 pol, {w.SB} subbands, "
+                               f"{'ci16' if w.sample_type == synth.CI16 else 'ci8' if w.sample_type == synth.CI8 else 'cf32'}, "
+                               f"16-tap PPF -> 64 ch, N={w.N} ({w.n_c} channel samples, {block_s:.8f} s)",
+                   "stations": w.S, "subbands": w.SB, "channels": w.C, "samples_per_block": w.N,
+                   "x_mode": w.x_mode},
+        "real_time_factor": round(block_s / (step_ms * 1e-3), 2),
+        "block_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                             "p99": round(float(np.percentile(lat, 99)), 3), "n": int(lat.size),
+                             "deadline_ms": round(block_s * 1e3, 3)},
+        "x_stage_tmacs": round(x_tmacs, 3),
+        "f_stage_gbs": round(f_gbs, 1),
+        "roofline": dominant,
+        "roofline_other": other,
+        "plain_fp32_form": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * cobalt.h - C ABI of the MI355X FX correlator (the correlator hot path of LOFAR's Cobalt,
+ * arXiv 1801.04834).
+ *
+ * One plan per observation setting.  Per ~1 s block of station samples the library runs
+ *   F stage: unpack -> polyphase FIR (history carried) -> C-point FFT -> fine delay
+ *            compensation + bandpass correction -> transpose to the cross-station layout
+ *            (+ precision conversion),
+ *   X stage: V[a][b] = sum_t Z_a(t) conj(Z_b(t)) over all station pairs and polarisations,
+ * as described in the paper's "Signal processing with GPU kernels" (sec. 7.5) and
+ * "Processing steps" (sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are DEVICE pointers (HIP global memory on the plan's device) owned
+ *    by the caller; they must be 16-byte aligned.  Pointers named h_* are host pointers;
+ *    the library copies what it needs before returning, so the caller may reuse them at
+ *    once.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
+ *    enqueues work and returns; results are ready when the stream reaches that point.
+ *    Successive calls on one plan are ordered even across streams (the plan waits on its
+ *    previous call's completion event).  Two host threads must not call into one plan at
+ *    the same time (COBALT_EBUSY).  Different plans may run concurrently.
+ *  - Return value: COBALT_OK (0) or a negative COBALT_E* code; cobalt_last_error() gives a
+ *    message (thread-local).  No C++ exception crosses this boundary.
+ *
+ * Notation: S stations (antenna fields), P = 2 polarisations, M = S*P inputs (input index
+ * a = s*P + p), SB subbands, C channels, T taps, N samples per input per subband per
+ * block, N_c = N / C channel samples, B = S(S+1)/2 baselines (s1 >= s2, autos included).
+ *
+ * Layouts (row-major, last index fastest)
+ * ---------------------------------------
+ *  input block   [S][P][SB][N] complex samples: int8 pairs (COBALT_CI8), int16 pairs
+ *                (COBALT_CI16) or float pairs (COBALT_CF32), (re, im) interleaved.
+ *  channelised   per channel (sb*C + c), planes x M rows x pitch channel samples:
+ *                 FP32 mode      [SB][C][M][pitch] float (re, im)
+ *                 FP16-split     [SB][C][2][M][pitch] _Float16 (re, im); plane 0 = hi,
+ *                                plane 1 = lo, hi + lo = 2^k * Z (k = fp16_prescale_log2)
+ *                 INT8 mode      [SB][C][M][pitch] int8 (re, im)
+ *                pitch = N_c rounded up to a multiple of 32; columns >= N_c are zero.
+ *  visibilities  [SB][C][B][4] complex: float (re, im) in FP32 / FP16-split modes,
+ *                int32 (re, im) raw integer sums in INT8 mode.  Baseline index
+ *                b(s1, s2) = s1(s1+1)/2 + s2 for s1 >= s2; pol pair q = 2*p1 + p2
+ *                (XX, XY, YX, YY); entry = sum_j Z[s1*P+p1][j] * conj(Z[s2*P+p2][j]).
+ */
+#ifndef COBALT_H
+#define COBALT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------------------ */
+#define COBALT_OK            0
+#define COBALT_EINVAL       -1   /* bad argument: sizes, NULL pointers, N % C != 0 ...   */
+#define COBALT_EUNSUPPORTED -2   /* valid but not built: C != 64, T != 16, P != 2, M > 160 in MFMA modes */
+#define COBALT_EOVERFLOW    -3   /* INT8 mode with N_c * 2 * 127^2 >= 2^31 (int32 sums)   */
+#define COBALT_ENOMEM       -4   /* device or pinned host allocation failed              */
+#define COBALT_EBUSY        -5   /* another host thread is inside a call on this plan    */
+#define COBALT_EDEVICE      -6   /* HIP runtime error; see cobalt_last_error()           */
+
+/* ---- sample types and X-stage modes -------------------------------------------------- */
+#define COBALT_CI8   1   /* complex int8 station samples (8-bit mode)                      */
+#define COBALT_CI16  2   /* complex int16 station samples (16-bit mode)                    */
+#define COBALT_CF32  3   /* complex float32 samples (exact test signals)                   */
+
+#define COBALT_X_FP32        0   /* FP32 channelised data, FP32 VALU correlator (plain form) */
+#define COBALT_X_FP16_SPLIT  1   /* FP16 hi/lo planes, FP16 MFMA (hh+hl+lh), FP32 accumulate */
+#define COBALT_X_INT8        2   /* int8 requantised data, int8 MFMA, int32 accumulate       */
+
+typedef struct cobalt_plan cobalt_plan;   /* opaque: workspace, FIR history, tables */
+
+/* Observation setting.  Host arrays are copied by cobalt_plan_create. */
+typedef struct cobalt_config {
+    int32_t n_stations;          /* S >= 1                                                */
+    int32_t n_pols;              /* P, must be 2                                          */
+    int32_t n_subbands;          /* SB >= 1                                               */
+    int32_t n_channels;          /* C, 64 (the only channel count built)                  */
+    int32_t n_taps;              /* T, 16 (the only tap count built)                      */
+    int32_t sample_type;         /* COBALT_CI8 | COBALT_CI16 | COBALT_CF32                */
+    int32_t x_mode;              /* COBALT_X_FP32 | COBALT_X_FP16_SPLIT | COBALT_X_INT8   */
+    int32_t fp16_prescale_log2;  /* k in [-24, 24]: FP16-split stores 2^k * Z; V is scaled
+                                    back by 2^-2k (exact).  Ignored in other modes.       */
+    int64_t samples_per_block;   /* N >= 0, multiple of C (196608 for ~1 s blocks)        */
+    double  sample_rate_hz;      /* f_s > 0, subband sample rate (195312.5)               */
+    float   requant_gain;        /* g > 0: INT8 mode stores clamp(rint(g * Z), +-127)      */
+    int32_t reserved0;           /* must be 0                                             */
+    const float*  h_fir;         /* [T*C] prototype FIR; output j, phase p uses
+                                    sum_t h[t*C+p] * x[(j-T+1+t)*C + p]                   */
+    const float*  h_bandpass;    /* [C] real bandpass correction per channel, or NULL (1) */
+    const double* h_subband_freq_hz; /* [SB] sky centre frequency of each subband (Hz)    */
+} cobalt_config;
+
+/* Sizes of one plan (filled by cobalt_plan_query). */
+typedef struct cobalt_plan_info {
+    int64_t n_channel_samples;   /* N_c = N / C                                           */
+    int64_t chan_pitch;          /* channel samples per channelised row (>= N_c)          */
+    int64_t n_baselines;         /* B = S(S+1)/2                                          */
+    int64_t input_bytes;         /* bytes of one input block                              */
+    int64_t chan_bytes;          /* bytes of the channelised buffer                       */
+    int64_t vis_bytes;           /* bytes of the visibility buffer                        */
+    int64_t workspace_bytes;     /* device bytes held by the plan                         */
+    int64_t useful_cmacs;        /* complex MACs per block: B * 4 * SB * C * N_c          */
+} cobalt_plan_info;
+
+/* Create a plan on the current HIP device: validates cfg, allocates the device workspace
+ * (channelised buffer, two FIR-history buffers zeroed, tables, delay staging) and copies
+ * the host tables.  On success *out owns everything; on failure *out is NULL and nothing
+ * is leaked.  Errors: EINVAL, EUNSUPPORTED, EOVERFLOW, ENOMEM, EDEVICE. */
+int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out);
+
+/* Device bytes cobalt_plan_create would allocate for cfg (for admission by HBM budget).
+ * Performs the same validation as create.  Allocates nothing. */
+int cobalt_estimate_bytes(const cobalt_config* cfg, size_t* device_bytes);
+
+/* Fill *info with the plan's sizes.  Errors: EINVAL (NULL). */
+int cobalt_plan_query(const cobalt_plan* plan, cobalt_plan_info* info);
+
+/* Full FX chain for one block: F stage into the plan's channelised buffer, then X stage
+ * into d_vis.  d_in: input block layout; h_delays: [S][2] float64 residual delays in
+ * seconds at block start and block end (fine delay compensation, sec. 7.5: phase
+ * exp(+2 pi i f_c tau(j)), tau linear in the channel sample j); d_vis: visibilities.
+ * Advances the FIR history.  Errors: EINVAL, EBUSY, EDEVICE. */
+int cobalt_correlate(cobalt_plan* plan, const void* d_in, const double* h_delays,
+                     void* d_vis, void* stream);
+
+/* F stage only: writes the channelised layout to d_chan (caller-owned, chan_bytes).
+ * Advances the FIR history exactly like cobalt_correlate.  Errors as cobalt_correlate. */
+int cobalt_channelize(cobalt_plan* plan, const void* d_in, const double* h_delays,
+                      void* d_chan, void* stream);
+
+/* X stage only, on a caller-provided channelised buffer in this plan's mode and layout
+ * (columns >= N_c are ignored).  Does not touch the FIR history.  Errors: EINVAL, EBUSY,
+ * EDEVICE. */
+int cobalt_correlate_channelized(cobalt_plan* plan, const void* d_chan, void* d_vis,
+                                 void* stream);
+
+/* Zero the FIR history (start of a new observation / after a gap in the stream).
+ * Errors: EINVAL, EBUSY, EDEVICE. */
+int cobalt_reset_history(cobalt_plan* plan, void* stream);
+
+/* Wait for the plan's last call, then free everything it owns.  NULL is a no-op.
+ * Errors: EDEVICE (the plan is freed anyway). */
+int cobalt_plan_destroy(cobalt_plan* plan);
+
+/* Message for the last error on this host thread ("" if none).  Never NULL. */
+const char* cobalt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COBALT_H */

@@ -1,0 +1,326 @@
+// F stage of the FX correlator for gfx950: unpack -> polyphase FIR (history carried) ->
+// 64-point FFT -> fine delay compensation + bandpass correction -> transpose to the
+// cross-station layout with precision conversion.
+//
+// The paper's correlator pipeline channelises each subband with FIR filters feeding an
+// FFT, carries the FIR history into the next block, applies fine delay compensation and
+// bandpass correction, and transposes on write-back so the correlator can work across
+// antenna fields ("Signal processing with GPU kernels", sec. 7.5).  Samples arrive as
+// fixed point and are converted to float ("Processing steps", sec. 3.2).  The delay phase
+// is formed in double precision; the rotation runs in single precision (sec. 7.5, sec. 8).
+//
+// Work decomposition (one wave64 per workgroup):
+//   workgroup = one input stream (station, polarisation, subband) x one chunk of 256
+//   channel samples, processed in passes of 32 channel samples.
+//   FIR:   lane p is FIR phase p; it keeps a 15-row sliding window in registers, so every
+//          input sample is read from HBM once (coalesced 64-lane rows).
+//   FFT:   the first radix-2 decimation-in-frequency stage runs across lanes p and p+32
+//          with v_permlane32_swap (two channel samples per swap); the two 32-point halves
+//          go through LDS so that lane (j, h) owns one 32-point DFT in registers.
+//   Delay: per (channel, sample) the phase in cycles f_c * tau(j) is formed with one FP64
+//          FMA and reduced with FP64 rint; the reduced phase is rotated in FP32 with the
+//          hardware sin/cos (argument in revolutions).
+//   Store: lanes with equal h write 32 consecutive channel samples of one channel row.
+#include "cobalt_internal.h"
+
+namespace cobalt {
+namespace {
+
+constexpr int kPass = 32;                 // channel samples per pass
+constexpr int kChunk = kFChunk;           // channel samples per workgroup (8 passes)
+constexpr int kRowF2 = 68;                // LDS row: two 32-point halves, 16 B apart
+constexpr int kHalfF2 = 34;
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+    double term = x, sum = x;
+    for (int n = 1; n < 24; ++n) { term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0)); sum += term; }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int n = 1; n < 24; ++n) { term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n)); sum += term; }
+    return sum;
+}
+// cos and sin of 2*pi*t/64 rounded to float, t in [0, 64)
+constexpr float tw_cos(int t) {
+    const int q = t / 16, r = t % 16;
+    const double th = 2.0 * kPi * r / 64.0, c = taylor_cos(th), s = taylor_sin(th);
+    return (float)(q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s);
+}
+constexpr float tw_sin(int t) {
+    const int q = t / 16, r = t % 16;
+    const double th = 2.0 * kPi * r / 64.0, c = taylor_cos(th), s = taylor_sin(th);
+    return (float)(q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c);
+}
+
+// (re + i im) * exp(-2 pi i t / 64), t a compile-time constant
+template <int t>
+__device__ __forceinline__ void rot_w64(float& re, float& im) {
+    if constexpr (t == 0) {
+        return;
+    } else if constexpr (t == 16) {
+        const float r = re;
+        re = im;
+        im = -r;
+    } else if constexpr (t == 8) {
+        constexpr float c = tw_cos(8);
+        const float r = re;
+        re = (r + im) * c;
+        im = (im - r) * c;
+    } else if constexpr (t == 24) {
+        constexpr float c = tw_sin(24);   // = 1/sqrt(2); cos(3 pi/4) = -c
+        const float r = re;
+        re = (im - r) * c;
+        im = -(im + r) * c;
+    } else {
+        constexpr float c = tw_cos(t), s = tw_sin(t);
+        const float r = re;
+        re = r * c + im * s;
+        im = im * c - r * s;
+    }
+}
+
+// One radix-2 decimation-in-frequency stage of a 32-point DFT (butterfly span `span`).
+template <int span, int k>
+__device__ __forceinline__ void dif_group(float (&re)[32], float (&im)[32], int start) {
+    if constexpr (k < span) {
+        const int i0 = start + k, i1 = i0 + span;
+        const float ar = re[i0], ai = im[i0], br = re[i1], bi = im[i1];
+        re[i0] = ar + br;
+        im[i0] = ai + bi;
+        float dr = ar - br, di = ai - bi;
+        rot_w64<k * (32 / span)>(dr, di);
+        re[i1] = dr;
+        im[i1] = di;
+        dif_group<span, k + 1>(re, im, start);
+    }
+}
+template <int span>
+__device__ __forceinline__ void dif_stage(float (&re)[32], float (&im)[32]) {
+#pragma unroll
+    for (int start = 0; start < 32; start += 2 * span) dif_group<span, 0>(re, im, start);
+}
+// Forward 32-point DFT, natural-order input; output element i holds bin bitrev5(i).
+__device__ __forceinline__ void fft32(float (&re)[32], float (&im)[32]) {
+    dif_stage<16>(re, im);
+    dif_stage<8>(re, im);
+    dif_stage<4>(re, im);
+    dif_stage<2>(re, im);
+    dif_stage<1>(re, im);
+}
+constexpr int bitrev5(int i) {
+    return ((i & 1) << 4) | ((i & 2) << 2) | (i & 4) | ((i & 8) >> 2) | ((i & 16) >> 4);
+}
+
+template <int ST> struct Samp;
+template <> struct Samp<ST_CI16> {
+    using raw_t = uint32_t;
+    static __device__ __forceinline__ float2 cvt(raw_t w) {
+        return make_float2((float)(int16_t)(w & 0xffffu), (float)((int32_t)w >> 16));
+    }
+};
+template <> struct Samp<ST_CI8> {
+    using raw_t = uint16_t;
+    static __device__ __forceinline__ float2 cvt(raw_t w) {
+        return make_float2((float)(int8_t)(w & 0xffu), (float)(int8_t)(w >> 8));
+    }
+};
+template <> struct Samp<ST_CF32> {
+    using raw_t = float2;
+    static __device__ __forceinline__ float2 cvt(raw_t w) { return w; }
+};
+
+struct __attribute__((aligned(4))) half2_t { _Float16 x, y; };
+struct __attribute__((aligned(2))) char2_t { int8_t x, y; };
+
+template <int ST, int OM>
+__global__ __launch_bounds__(64) void fstage_kernel(FArgs a) {
+    using S_ = Samp<ST>;
+    using raw_t = typename S_::raw_t;
+    __shared__ float2 ylds[kPass * kRowF2];
+
+    const int lane = threadIdx.x;
+    const int chunk = (int)(blockIdx.x % (unsigned)a.n_chunks);
+    const int64_t st = (int64_t)(blockIdx.x / (unsigned)a.n_chunks);   // (s*P + p)*SB + sb
+    const int sb = (int)(st % a.SB);
+    const int row_in = (int)(st / a.SB);                                 // input index s*P + p
+    const int s = row_in >> 1;
+    const raw_t* __restrict__ in = (const raw_t*)a.in + st * a.N;
+    const raw_t* __restrict__ hold = (const raw_t*)a.hist_old + st * kHist;
+
+    // The last chunk of every stream writes the history for the next block: the final
+    // (T-1)*C samples of [old history, block].
+    if (chunk == a.n_chunks - 1) {
+        raw_t* hnew = (raw_t*)a.hist_new + st * kHist;
+        for (int i = lane; i < kHist; i += 64) {
+            const int64_t t = a.N + i;
+            hnew[i] = t < kHist ? hold[t] : in[t - kHist];
+        }
+    }
+
+    float h[kT];
+#pragma unroll
+    for (int t = 0; t < kT; ++t) h[t] = a.fir[t * kC + lane];
+
+    float wsn, wcs;                            // exp(-2 pi i q / 64), q = lane mod 32
+    sincospif((float)(lane & 31) / 32.0f, &wsn, &wcs);
+
+    const double tau0 = a.delays[2 * s], tau1 = a.delays[2 * s + 1];
+    const double fsb = a.f_sb[sb];
+    const int jj = lane >> 1, hh = lane & 1;
+
+    auto load_row = [&](int r) -> raw_t {      // r is wave-uniform
+        if (r < 0) return hold[(r + kHistRows) * kC + lane];
+        if (r < a.n_c) return in[(int64_t)r * kC + lane];
+        return raw_t{};
+    };
+
+    const int j0 = chunk * kChunk;
+    const int jend = min(j0 + kChunk, a.pitch);
+
+    float2 tail[kHistRows];
+#pragma unroll
+    for (int i = 0; i < kHistRows; ++i) tail[i] = S_::cvt(load_row(j0 - kHistRows + i));
+
+    for (int jb = j0; jb < jend; jb += kPass) {
+        raw_t nw[kPass];
+#pragma unroll
+        for (int r = 0; r < kPass; ++r) nw[r] = load_row(jb + r);
+
+        // ---- polyphase FIR: y_j[p] = sum_t h[t*C + p] x[(j - T + 1 + t)*C + p] ----
+        float2 acc[kPass];
+#pragma unroll
+        for (int j = 0; j < kPass; ++j) {
+            float yr = 0.f, yi = 0.f;
+#pragma unroll
+            for (int t = 0; t < kT; ++t) {
+                const int w = j + t;             // window row: < 15 from the tail
+                const float2 x = w < kHistRows ? tail[w] : S_::cvt(nw[w - kHistRows]);
+                yr = fmaf(h[t], x.x, yr);
+                yi = fmaf(h[t], x.y, yi);
+            }
+            acc[j] = make_float2(yr, yi);
+        }
+#pragma unroll
+        for (int i = 0; i < kHistRows; ++i) tail[i] = S_::cvt(nw[kPass - kHistRows + i]);
+
+        // ---- first DIF stage across lanes p, p+32 (two channel samples per swap) ----
+#pragma unroll
+        for (int pr = 0; pr < kPass / 2; ++pr) {
+            const float2 A = acc[2 * pr], B = acc[2 * pr + 1];
+            const auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.x), __float_as_uint(B.x), false, false);
+            const auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.y), __float_as_uint(B.y), false, false);
+            // lanes < 32: (y_j[q], y_j[q+32]) of j = 2pr; lanes >= 32: same for j = 2pr+1
+            const float r0r = __uint_as_float(sr[0]), r1r = __uint_as_float(sr[1]);
+            const float r0i = __uint_as_float(si[0]), r1i = __uint_as_float(si[1]);
+            const float dr = r0r - r1r, di = r0i - r1i;
+            const int row = 2 * pr + (lane >> 5), q = lane & 31;
+            ylds[row * kRowF2 + q] = make_float2(r0r + r1r, r0i + r1i);
+            ylds[row * kRowF2 + kHalfF2 + q] = make_float2(dr * wcs + di * wsn, di * wcs - dr * wsn);
+        }
+        __syncthreads();
+
+        // ---- 32-point DFT of the even (h = 0) or odd (h = 1) output bins ----
+        float xr[32], xi[32];
+        const float2* src = &ylds[jj * kRowF2 + hh * kHalfF2];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const float2 v = src[q];
+            xr[q] = v.x;
+            xi[q] = v.y;
+        }
+        __syncthreads();
+        fft32(xr, xi);
+
+        // ---- fine delay + bandpass, then write channel rows ----
+        const int j = jb + jj;
+        const bool live = j < a.n_c;
+        const double tau = tau0 + (tau1 - tau0) * (double)j / (double)a.n_c;
+        const double c1 = tau * a.df;                  // cycles per channel step
+        const double c0 = fma((double)hh, c1, tau * fsb);
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const int m = bitrev5(i);                  // this register holds bin 2m + hh
+            const int m2 = 2 * m - (m >= 16 ? 64 : 0); // signed bin offset minus hh
+            const int c_even = (2 * m + 32) & 63;
+            const double cyc = fma((double)m2, c1, c0);
+            const float r = (float)(cyc - rint(cyc));
+            const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+            const float b = hh ? a.bscale[c_even + 1] : a.bscale[c_even];
+            const float pr_ = cs * b, pi_ = sn * b;
+            float zr = xr[i] * pr_ - xi[i] * pi_;
+            float zi = xr[i] * pi_ + xi[i] * pr_;
+            if (!live) { zr = 0.f; zi = 0.f; }
+            const int c = c_even + hh;
+            const int64_t ch = (int64_t)sb * kC + c;
+            if constexpr (OM == XM_FP32) {
+                float2* out = (float2*)a.out;
+                out[(ch * a.M + row_in) * a.pitch + j] = make_float2(zr, zi);
+            } else if constexpr (OM == XM_FP16_SPLIT) {
+                half2_t hi, lo;
+                hi.x = (_Float16)zr;
+                hi.y = (_Float16)zi;
+                lo.x = (_Float16)(zr - (float)hi.x);
+                lo.y = (_Float16)(zi - (float)hi.y);
+                half2_t* out = (half2_t*)a.out;
+                const int64_t plane = (int64_t)a.M * a.pitch;
+                const int64_t base = ch * 2 * plane + (int64_t)row_in * a.pitch + j;
+                out[base] = hi;
+                out[base + plane] = lo;
+            } else {
+                const float qr = fminf(fmaxf(rintf(zr), -127.f), 127.f);
+                const float qi = fminf(fmaxf(rintf(zi), -127.f), 127.f);
+                char2_t v;
+                v.x = (int8_t)(int)qr;
+                v.y = (int8_t)(int)qi;
+                char2_t* out = (char2_t*)a.out;
+                out[(ch * a.M + row_in) * a.pitch + j] = v;
+            }
+        }
+    }
+}
+
+__global__ void zero_fill_kernel(uint4* p, int64_t n16, uint8_t* tail, int64_t ntail) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0)
+        for (int64_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
+}
+
+template <int ST>
+hipError_t launch_st(int x_mode, const FArgs& a, int n_streams, hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)n_streams * a.n_chunks)), block(64);
+    switch (x_mode) {
+        case XM_FP32: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP32>), grid, block, 0, st, a); break;
+        case XM_FP16_SPLIT: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP16_SPLIT>), grid, block, 0, st, a); break;
+        case XM_INT8: hipLaunchKernelGGL((fstage_kernel<ST, XM_INT8>), grid, block, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fstage(int sample_type, int x_mode, const FArgs& a, int n_streams, hipStream_t st) {
+    if (n_streams <= 0 || a.n_chunks <= 0) return hipSuccess;
+    switch (sample_type) {
+        case ST_CI8: return launch_st<ST_CI8>(x_mode, a, n_streams, st);
+        case ST_CI16: return launch_st<ST_CI16>(x_mode, a, n_streams, st);
+        case ST_CF32: return launch_st<ST_CF32>(x_mode, a, n_streams, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_zero_fill(void* p, int64_t bytes, hipStream_t st) {
+    if (bytes <= 0) return hipSuccess;
+    const int64_t n16 = ((uintptr_t)p % 16 == 0) ? bytes / 16 : 0;
+    const int64_t ntail = bytes - n16 * 16;
+    const int64_t blocks = n16 > 0 ? (n16 + 255) / 256 : 1;
+    const unsigned g = (unsigned)(blocks < 4096 ? blocks : 4096);
+    hipLaunchKernelGGL(zero_fill_kernel, dim3(g), dim3(256), 0, st, (uint4*)p, n16, (uint8_t*)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+}  // namespace cobalt

@@ -1,0 +1,431 @@
+// C ABI of libcobalt.so (declared in include/cobalt.h): plan validation, device workspace,
+// FIR history, per-call delay staging and kernel launches.
+//
+// The paper wraps every GPU kernel in a class that owns its launch configuration and
+// buffer sizes and documents which buffers each kernel reads and writes ("Signal
+// processing with GPU kernels", sec. 7.5); it allocates buffers once at initialisation
+// and keeps a few device buffers that kernels alternate between (sec. 7.1, sec. 7.5).
+// Here the plan plays that role: one allocation at create, the two FIR-history buffers
+// alternate between blocks, and observation constants are fixed at create.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "../../include/cobalt.h"
+#include "cobalt_internal.h"
+
+using namespace cobalt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+constexpr int kRing = 8;   // delay staging slots (pinned host + device)
+
+struct Sizes {
+    int64_t S, P, SB, C, T, N, n_c, pitch, M, B, streams;
+    int64_t sample_bytes, input_bytes, chan_elem_bytes, chan_planes, chan_stride, chan_bytes, vis_bytes;
+    int64_t hist_bytes, table_bytes, workspace_bytes;
+};
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int validate(const cobalt_config* c, Sizes* z) {
+    if (!c) return fail(COBALT_EINVAL, "cfg is NULL");
+    if (c->n_stations < 1) return fail(COBALT_EINVAL, "n_stations must be >= 1 (got %d)", c->n_stations);
+    if (c->n_pols != 2) return fail(c->n_pols < 1 ? COBALT_EINVAL : COBALT_EUNSUPPORTED, "n_pols must be 2 (got %d)", c->n_pols);
+    if (c->n_subbands < 1) return fail(COBALT_EINVAL, "n_subbands must be >= 1 (got %d)", c->n_subbands);
+    if (c->n_channels < 1 || c->n_taps < 1) return fail(COBALT_EINVAL, "n_channels and n_taps must be >= 1");
+    if (c->n_channels != kC) return fail(COBALT_EUNSUPPORTED, "only %d channels are built (got %d)", kC, c->n_channels);
+    if (c->n_taps != kT) return fail(COBALT_EUNSUPPORTED, "only %d taps are built (got %d)", kT, c->n_taps);
+    if (c->sample_type != COBALT_CI8 && c->sample_type != COBALT_CI16 && c->sample_type != COBALT_CF32)
+        return fail(COBALT_EINVAL, "unknown sample_type %d", c->sample_type);
+    if (c->x_mode != COBALT_X_FP32 && c->x_mode != COBALT_X_FP16_SPLIT && c->x_mode != COBALT_X_INT8)
+        return fail(COBALT_EINVAL, "unknown x_mode %d", c->x_mode);
+    if (c->samples_per_block < 0 || c->samples_per_block % c->n_channels != 0)
+        return fail(COBALT_EINVAL, "samples_per_block (%lld) must be >= 0 and a multiple of n_channels",
+                    (long long)c->samples_per_block);
+    if (!(c->sample_rate_hz > 0.0) || !std::isfinite(c->sample_rate_hz))
+        return fail(COBALT_EINVAL, "sample_rate_hz must be finite and > 0");
+    if (c->reserved0 != 0) return fail(COBALT_EINVAL, "reserved0 must be 0");
+    if (!c->h_fir) return fail(COBALT_EINVAL, "h_fir is NULL");
+    if (!c->h_subband_freq_hz) return fail(COBALT_EINVAL, "h_subband_freq_hz is NULL");
+    for (int i = 0; i < kT * kC; ++i)
+        if (!std::isfinite(c->h_fir[i])) return fail(COBALT_EINVAL, "h_fir[%d] is not finite", i);
+    if (c->h_bandpass)
+        for (int i = 0; i < kC; ++i)
+            if (!std::isfinite(c->h_bandpass[i])) return fail(COBALT_EINVAL, "h_bandpass[%d] is not finite", i);
+    for (int i = 0; i < c->n_subbands; ++i)
+        if (!std::isfinite(c->h_subband_freq_hz[i])) return fail(COBALT_EINVAL, "h_subband_freq_hz[%d] is not finite", i);
+
+    Sizes s{};
+    s.S = c->n_stations; s.P = c->n_pols; s.SB = c->n_subbands; s.C = kC; s.T = kT;
+    s.N = c->samples_per_block; s.n_c = s.N / kC; s.M = s.S * s.P; s.B = s.S * (s.S + 1) / 2;
+    s.pitch = round_up(s.n_c, kPitchAlign);
+    s.streams = s.M * s.SB;
+    if (s.n_c > (int64_t)1 << 30) return fail(COBALT_EINVAL, "samples_per_block too large");
+    if (c->x_mode == COBALT_X_FP32) {
+        if (s.M > kMaxFp32Inputs)
+            return fail(COBALT_EUNSUPPORTED, "FP32 mode supports up to %d inputs (got %lld)", kMaxFp32Inputs, (long long)s.M);
+    } else if (s.M > kMaxMfmaInputs) {
+        return fail(COBALT_EUNSUPPORTED, "MFMA modes support up to %d inputs (%d stations); got %lld",
+                    kMaxMfmaInputs, kMaxMfmaInputs / 2, (long long)s.M);
+    }
+    if (c->x_mode == COBALT_X_INT8) {
+        if (!(c->requant_gain > 0.f) || !std::isfinite(c->requant_gain))
+            return fail(COBALT_EINVAL, "requant_gain must be finite and > 0");
+        if (s.n_c * 2 * 127 * 127 >= ((int64_t)1 << 31))
+            return fail(COBALT_EOVERFLOW, "INT8 mode: N_c * 2 * 127^2 = %lld overflows int32 (N_c = %lld)",
+                        (long long)(s.n_c * 2 * 127 * 127), (long long)s.n_c);
+    }
+    if (c->x_mode == COBALT_X_FP16_SPLIT && (c->fp16_prescale_log2 < -24 || c->fp16_prescale_log2 > 24))
+        return fail(COBALT_EINVAL, "fp16_prescale_log2 must lie in [-24, 24]");
+
+    s.sample_bytes = c->sample_type == COBALT_CI8 ? 2 : c->sample_type == COBALT_CI16 ? 4 : 8;
+    s.input_bytes = s.streams * s.N * s.sample_bytes;
+    s.chan_elem_bytes = c->x_mode == COBALT_X_INT8 ? 2 : c->x_mode == COBALT_X_FP16_SPLIT ? 4 : 8;
+    s.chan_planes = c->x_mode == COBALT_X_FP16_SPLIT ? 2 : 1;
+    s.chan_stride = s.chan_planes * s.M * s.pitch * s.chan_elem_bytes;
+    s.chan_bytes = s.SB * kC * s.chan_stride;
+    s.vis_bytes = s.SB * kC * s.B * 4 * 8;
+    s.hist_bytes = s.streams * kHist * s.sample_bytes;
+    s.table_bytes = round_up((int64_t)kT * kC * 4, 256) + round_up(kC * 4, 256) + round_up(s.SB * 8, 256) +
+                    kRing * round_up(s.S * 16, 256);
+    s.workspace_bytes = round_up(s.chan_bytes, 256) + 2 * round_up(s.hist_bytes, 256) + s.table_bytes;
+    *z = s;
+    return COBALT_OK;
+}
+
+}  // namespace
+
+struct cobalt_plan {
+    cobalt_config cfg;           // host pointers cleared after create
+    Sizes z;
+    int device = 0;
+    char* d_ws = nullptr;        // one allocation for the whole workspace
+    void* d_chan = nullptr;
+    void* d_hist[2] = {nullptr, nullptr};
+    int hist_cur = 0;
+    float* d_fir = nullptr;
+    float* d_bscale = nullptr;
+    double* d_fsb = nullptr;
+    double* d_delay[kRing] = {};
+    double* h_delay = nullptr;   // pinned [kRing][S][2]
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_used[kRing] = {};
+    int ring_next = 0;
+    hipEvent_t done_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
+    std::mutex mu;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; prev = -1; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(COBALT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_plan(cobalt_plan* p) {
+    if (!p) return;
+    for (int i = 0; i < kRing; ++i)
+        if (p->ring_ev[i]) (void)hipEventDestroy(p->ring_ev[i]);
+    if (p->done_ev) (void)hipEventDestroy(p->done_ev);
+    if (p->h_delay) (void)hipHostFree(p->h_delay);
+    if (p->d_ws) (void)hipFree(p->d_ws);
+    delete p;
+}
+
+// Order this call after the plan's previous call when it came on another stream.
+int begin_call(cobalt_plan* p, hipStream_t st) {
+    if (p->has_last && p->last_stream != st) {
+        hipError_t e = hipStreamWaitEvent(st, p->done_ev, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    return COBALT_OK;
+}
+
+int end_call(cobalt_plan* p, hipStream_t st) {
+    hipError_t e = hipEventRecord(p->done_ev, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->last_stream = st;
+    p->has_last = true;
+    return COBALT_OK;
+}
+
+// Copy the caller's delays into a ring slot (pinned host -> device) on stream st.
+int stage_delays(cobalt_plan* p, const double* h_delays, hipStream_t st, const double** d_out) {
+    const int S = (int)p->z.S;
+    for (int i = 0; i < 2 * S; ++i)
+        if (!std::isfinite(h_delays[i])) return fail(COBALT_EINVAL, "h_delays[%d] is not finite", i);
+    const int slot = p->ring_next;
+    p->ring_next = (p->ring_next + 1) % kRing;
+    if (p->ring_used[slot]) {
+        hipError_t e = hipEventSynchronize(p->ring_ev[slot]);   // the slot's previous copy has run
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    double* h = p->h_delay + (size_t)slot * 2 * S;
+    std::memcpy(h, h_delays, sizeof(double) * 2 * S);
+    hipError_t e = hipMemcpyAsync(p->d_delay[slot], h, sizeof(double) * 2 * S, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(delays)");
+    e = hipEventRecord(p->ring_ev[slot], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(delays)");
+    p->ring_used[slot] = true;
+    *d_out = p->d_delay[slot];
+    return COBALT_OK;
+}
+
+int run_fstage(cobalt_plan* p, const void* d_in, const double* d_delays, void* d_chan, hipStream_t st) {
+    const Sizes& z = p->z;
+    if (z.n_c == 0) return COBALT_OK;       // empty block: nothing to filter, history unchanged
+    FArgs a{};
+    a.in = d_in;
+    a.hist_old = p->d_hist[p->hist_cur];
+    a.hist_new = p->d_hist[p->hist_cur ^ 1];
+    a.out = d_chan;
+    a.fir = p->d_fir;
+    a.bscale = p->d_bscale;
+    a.f_sb = p->d_fsb;
+    a.delays = d_delays;
+    a.N = z.N;
+    a.S = (int)z.S;
+    a.SB = (int)z.SB;
+    a.M = (int)z.M;
+    a.n_c = (int)z.n_c;
+    a.pitch = (int)z.pitch;
+    a.n_chunks = (int)((z.pitch + kFChunk - 1) / kFChunk);
+    a.df = p->cfg.sample_rate_hz / kC;
+    hipError_t e = launch_fstage(p->cfg.sample_type, p->cfg.x_mode, a, (int)z.streams, st);
+    if (e != hipSuccess) return hip_fail(e, "F-stage launch");
+    p->hist_cur ^= 1;
+    return COBALT_OK;
+}
+
+int run_xstage(cobalt_plan* p, const void* d_chan, void* d_vis, hipStream_t st) {
+    const Sizes& z = p->z;
+    XArgs a{};
+    a.chan = d_chan;
+    a.vis = d_vis;
+    a.chan_stride = z.chan_stride;
+    a.M = (int)z.M;
+    a.S = (int)z.S;
+    a.n_c = (int)z.n_c;
+    a.pitch = (int)z.pitch;
+    a.n_chan = (int)(z.SB * kC);
+    a.n_blocks8 = (int)((z.M + 7) / 8);
+    a.out_scale = std::ldexp(1.0f, -2 * p->cfg.fp16_prescale_log2);
+    hipError_t e = p->cfg.x_mode == COBALT_X_FP32 ? launch_xstage_fp32(a, st) : launch_xstage_mfma(p->cfg.x_mode, a, st);
+    if (e != hipSuccess) return hip_fail(e, "X-stage launch");
+    return COBALT_OK;
+}
+
+struct CallLock {
+    std::unique_lock<std::mutex> lk;
+    explicit CallLock(cobalt_plan* p) : lk(p->mu, std::try_to_lock) {}
+    bool owns() const { return lk.owns_lock(); }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* cobalt_last_error(void) { return g_last_error.c_str(); }
+
+int cobalt_estimate_bytes(const cobalt_config* cfg, size_t* device_bytes) {
+    g_last_error.clear();
+    if (!device_bytes) return fail(COBALT_EINVAL, "device_bytes is NULL");
+    Sizes z;
+    int rc = validate(cfg, &z);
+    if (rc != COBALT_OK) return rc;
+    *device_bytes = (size_t)z.workspace_bytes;
+    return COBALT_OK;
+}
+
+int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) {
+    g_last_error.clear();
+    if (!out) return fail(COBALT_EINVAL, "out is NULL");
+    *out = nullptr;
+    Sizes z;
+    int rc = validate(cfg, &z);
+    if (rc != COBALT_OK) return rc;
+
+    cobalt_plan* p = new (std::nothrow) cobalt_plan();
+    if (!p) return fail(COBALT_ENOMEM, "host allocation failed");
+    p->cfg = *cfg;
+    p->cfg.h_fir = nullptr;
+    p->cfg.h_bandpass = nullptr;
+    p->cfg.h_subband_freq_hz = nullptr;
+    p->z = z;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
+
+    e = hipMalloc((void**)&p->d_ws, (size_t)z.workspace_bytes);
+    if (e != hipSuccess) {
+        free_plan(p);
+        (void)hipGetLastError();
+        return fail(COBALT_ENOMEM, "hipMalloc(%lld bytes) failed: %s", (long long)z.workspace_bytes, hipGetErrorString(e));
+    }
+    char* q = p->d_ws;
+    p->d_chan = q;                q += round_up(z.chan_bytes, 256);
+    p->d_hist[0] = q;             q += round_up(z.hist_bytes, 256);
+    p->d_hist[1] = q;             q += round_up(z.hist_bytes, 256);
+    p->d_fir = (float*)q;         q += round_up((int64_t)kT * kC * 4, 256);
+    p->d_bscale = (float*)q;      q += round_up(kC * 4, 256);
+    p->d_fsb = (double*)q;        q += round_up(z.SB * 8, 256);
+    for (int i = 0; i < kRing; ++i) { p->d_delay[i] = (double*)q; q += round_up(z.S * 16, 256); }
+
+    e = hipHostMalloc((void**)&p->h_delay, sizeof(double) * 2 * z.S * kRing, hipHostMallocDefault);
+    if (e != hipSuccess) { free_plan(p); (void)hipGetLastError(); return fail(COBALT_ENOMEM, "hipHostMalloc failed"); }
+    for (int i = 0; i < kRing; ++i) {
+        e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipEventCreate"); }
+    }
+    e = hipEventCreateWithFlags(&p->done_ev, hipEventDisableTiming);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipEventCreate"); }
+
+    // tables: FIR, bandpass x mode scale (2^k, requant gain, or 1), subband frequencies
+    float bscale[kC];
+    const double mode_scale = cfg->x_mode == COBALT_X_FP16_SPLIT ? std::ldexp(1.0, cfg->fp16_prescale_log2)
+                              : cfg->x_mode == COBALT_X_INT8   ? (double)cfg->requant_gain
+                                                               : 1.0;
+    for (int c = 0; c < kC; ++c) bscale[c] = (float)((cfg->h_bandpass ? (double)cfg->h_bandpass[c] : 1.0) * mode_scale);
+    e = hipMemcpy(p->d_fir, cfg->h_fir, sizeof(float) * kT * kC, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_bscale, bscale, sizeof bscale, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_fsb, cfg->h_subband_freq_hz, sizeof(double) * z.SB, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "table upload"); }
+    // FIR history starts at zero (no samples before the first block)
+    e = launch_zero_fill(p->d_hist[0], round_up(z.hist_bytes, 256) * 2, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "history init"); }
+    *out = p;
+    return COBALT_OK;
+}
+
+int cobalt_plan_query(const cobalt_plan* p, cobalt_plan_info* info) {
+    g_last_error.clear();
+    if (!p || !info) return fail(COBALT_EINVAL, "plan or info is NULL");
+    const Sizes& z = p->z;
+    info->n_channel_samples = z.n_c;
+    info->chan_pitch = z.pitch;
+    info->n_baselines = z.B;
+    info->input_bytes = z.input_bytes;
+    info->chan_bytes = z.chan_bytes;
+    info->vis_bytes = z.vis_bytes;
+    info->workspace_bytes = z.workspace_bytes;
+    info->useful_cmacs = z.B * 4 * z.SB * kC * z.n_c;
+    return COBALT_OK;
+}
+
+static int do_fx(cobalt_plan* p, const void* d_in, const double* h_delays, void* d_chan, void* d_vis, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    if ((!d_in && p->z.input_bytes > 0) || !h_delays) return fail(COBALT_EINVAL, "d_in or h_delays is NULL");
+    if (!d_chan && !d_vis) return fail(COBALT_EINVAL, "output pointer is NULL");
+    if (((uintptr_t)d_in | (uintptr_t)d_chan | (uintptr_t)d_vis) % 16)
+        return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
+    CallLock lock(p);
+    if (!lock.owns()) return fail(COBALT_EBUSY, "plan is in use by another host thread");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = begin_call(p, st);
+    if (rc) return rc;
+    const double* d_delays = nullptr;
+    rc = stage_delays(p, h_delays, st, &d_delays);
+    if (rc) return rc;
+    void* chan = d_chan ? d_chan : p->d_chan;
+    rc = run_fstage(p, d_in, d_delays, chan, st);
+    if (rc) return rc;
+    if (d_vis) {
+        rc = run_xstage(p, chan, d_vis, st);
+        if (rc) return rc;
+    }
+    return end_call(p, st);
+}
+
+int cobalt_correlate(cobalt_plan* p, const void* d_in, const double* h_delays, void* d_vis, void* stream) {
+    if (!d_vis) { g_last_error = "d_vis is NULL"; return COBALT_EINVAL; }
+    return do_fx(p, d_in, h_delays, nullptr, d_vis, stream);
+}
+
+int cobalt_channelize(cobalt_plan* p, const void* d_in, const double* h_delays, void* d_chan, void* stream) {
+    if (!d_chan) { g_last_error = "d_chan is NULL"; return COBALT_EINVAL; }
+    return do_fx(p, d_in, h_delays, d_chan, nullptr, stream);
+}
+
+int cobalt_correlate_channelized(cobalt_plan* p, const void* d_chan, void* d_vis, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    if ((!d_chan && p->z.chan_bytes > 0) || !d_vis) return fail(COBALT_EINVAL, "d_chan or d_vis is NULL");
+    if (((uintptr_t)d_chan | (uintptr_t)d_vis) % 16) return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
+    CallLock lock(p);
+    if (!lock.owns()) return fail(COBALT_EBUSY, "plan is in use by another host thread");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = begin_call(p, st);
+    if (rc) return rc;
+    rc = run_xstage(p, d_chan, d_vis, st);
+    if (rc) return rc;
+    return end_call(p, st);
+}
+
+int cobalt_reset_history(cobalt_plan* p, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    CallLock lock(p);
+    if (!lock.owns()) return fail(COBALT_EBUSY, "plan is in use by another host thread");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = begin_call(p, st);
+    if (rc) return rc;
+    hipError_t e = launch_zero_fill(p->d_hist[p->hist_cur], round_up(p->z.hist_bytes, 256), st);
+    if (e != hipSuccess) return hip_fail(e, "history reset");
+    return end_call(p, st);
+}
+
+int cobalt_plan_destroy(cobalt_plan* p) {
+    g_last_error.clear();
+    if (!p) return COBALT_OK;
+    int rc = COBALT_OK;
+    {
+        DeviceGuard dg(p->device);
+        if (p->has_last) {
+            hipError_t e = hipEventSynchronize(p->done_ev);
+            if (e != hipSuccess) rc = hip_fail(e, "hipEventSynchronize(destroy)");
+        }
+        free_plan(p);
+    }
+    return rc;
+}
+
+}  // extern "C"

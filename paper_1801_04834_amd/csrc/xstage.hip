@@ -1,0 +1,359 @@
+// X stage of the FX correlator for gfx950: per channel, V = Z Z^H over all inputs
+// (station x polarisation), integrated over the block ("Signal processing with GPU
+// kernels", sec. 7.5: correlations of all pairs of antenna fields, averaged to ~1 s).
+//
+// MFMA form (FP16-split and int8): a complex Hermitian rank-K update written as two real
+// contractions over K = 2 N_c interleaved (re, im) values:
+//     Re V[a][b] = sum_k A[a][k] A[b][k]         (A = interleaved rows of Z)
+//     Im V[a][b] = sum_k A[a][k] A'[b][k]        (A' = per sample (re, im) -> (-im, re))
+// One workgroup owns one channel and keeps every lower-triangle 32x32 tile of V in
+// accumulators; channel rows stream through LDS once.  An MFMA fragment of row block I
+// (lane i: row 32I + i%32, 8 halves / 16 bytes of K) is simultaneously an A operand (row
+// I) and a B operand (column I), so both operands of a tile come from the same LDS reads
+// and the k order inside a fragment never matters.  A' is built in registers from the
+// B-role fragments.
+//   FP16-split: Z*2^k = hi + lo (two fp16 planes); V ~= hh + hl + lh accumulated in FP32
+//   (the dropped lo*lo term is below 2^-22 of |Z|^2), scaled back by 2^-2k.
+//   int8: exact int32 sums.
+// Plain FP32 form: 8x8 register blocks of complex FMAs on the VALU.
+#include <type_traits>
+
+#include "cobalt_internal.h"
+
+namespace cobalt {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for_impl(F& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for_impl<I + 1, N>(f);
+    }
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) { static_for_impl<0, N>(f); }
+
+// Lower-triangle tiles of an R x R block grid, column-major: (0,0),(1,0)..(R-1,0),(1,1)..
+constexpr int tile_count(int R) { return R * (R + 1) / 2; }
+constexpr int tile_J(int R, int idx) {
+    int J = 0;
+    while (idx >= R - J) { idx -= R - J; ++J; }
+    return J;
+}
+constexpr int tile_I(int R, int idx) {
+    int J = 0;
+    while (idx >= R - J) { idx -= R - J; ++J; }
+    return J + idx;
+}
+constexpr int kTilesPerWave = 4;
+// blocks used by wave W as A (row) or B (column) operands
+constexpr unsigned wave_blocks(int R, int W, bool as_b) {
+    unsigned m = 0;
+    for (int t = kTilesPerWave * W; t < kTilesPerWave * W + kTilesPerWave && t < tile_count(R); ++t)
+        m |= 1u << (as_b ? tile_J(R, t) : tile_I(R, t));
+    return m;
+}
+
+template <int MODE> struct XCfg;
+template <> struct XCfg<XM_FP16_SPLIT> {
+    static constexpr int kKc = 32;            // complex samples per LDS chunk
+    static constexpr int kRowB = 272;         // hi 128 B + lo 128 B + 16 B pad
+    static constexpr int kSteps = 4;          // k-steps of 16 halves per chunk
+    using acc_t = floatx16;
+    using frag_t = half8;
+};
+template <> struct XCfg<XM_INT8> {
+    static constexpr int kKc = 64;
+    static constexpr int kRowB = 144;         // 128 B + 16 B pad
+    static constexpr int kSteps = 4;          // k-steps of 32 bytes per chunk
+    using acc_t = intx16;
+    using frag_t = intx4;
+};
+
+// (re, im) -> (-im, re) on packed fp16 pairs
+__device__ __forceinline__ uintx4 swapneg_f16(uintx4 d) {
+    uintx4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = __builtin_amdgcn_alignbit(d[e], d[e], 16) ^ 0x00008000u;
+    return r;
+}
+// (re, im) -> (-im, re) on packed int8 pairs; inputs lie in [-127, 127]
+__device__ __forceinline__ uintx4 swapneg_i8(uintx4 d) {
+    uintx4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const unsigned t = __builtin_amdgcn_perm(d[e], d[e], 0x02030001u);   // bytes (im, re) pairs
+        const unsigned lo = t & 0x00ff00ffu;
+        r[e] = (t & 0xff00ff00u) | ((0x01000100u - lo) & 0x00ff00ffu);
+    }
+    return r;
+}
+
+// Stage one K chunk of all R*32 rows into LDS (rows >= M and columns >= N_c are zero).
+template <int MODE, int R>
+__device__ __forceinline__ void stage_chunk(const XArgs& a, const char* __restrict__ chan, char* lds, int kc0, int tid) {
+    using C_ = XCfg<MODE>;
+    if constexpr (MODE == XM_FP16_SPLIT) {
+        const int64_t plane = (int64_t)a.M * a.pitch * 4;
+        for (int id = tid; id < R * 32 * 16; id += 256) {
+            const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
+            const int col0 = kc0 + seg * 4;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (row < a.M) {
+                v = *(const uint4*)(chan + pl * plane + ((int64_t)row * a.pitch + col0) * 4);
+                if (col0 + 0 >= a.n_c) v.x = 0;
+                if (col0 + 1 >= a.n_c) v.y = 0;
+                if (col0 + 2 >= a.n_c) v.z = 0;
+                if (col0 + 3 >= a.n_c) v.w = 0;
+            }
+            *(uint4*)(lds + row * C_::kRowB + pl * 128 + seg * 16) = v;
+        }
+    } else {
+        for (int id = tid; id < R * 32 * 8; id += 256) {
+            const int row = id >> 3, seg = id & 7;
+            const int col0 = kc0 + seg * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (row < a.M && col0 < a.pitch) {
+                v = *(const uint4*)(chan + ((int64_t)row * a.pitch + col0) * 2);
+                const int keep = a.n_c - col0;                 // complex samples to keep
+                if (keep < 8) {
+                    unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k0 = 2 * e;                  // two char2 per dword
+                        if (k0 >= keep) w[e] = 0;
+                        else if (k0 + 1 >= keep) w[e] &= 0x0000ffffu;
+                    }
+                    v = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+            *(uint4*)(lds + row * C_::kRowB + seg * 16) = v;
+        }
+    }
+}
+
+template <int MODE, int R, int W>
+__device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ chan, char* lds, int tid) {
+    using C_ = XCfg<MODE>;
+    using acc_t = typename C_::acc_t;
+    using frag_t = typename C_::frag_t;
+    constexpr int NT = tile_count(R);
+    constexpr int T0 = kTilesPerWave * W;
+    constexpr int NW = NT - T0 <= 0 ? 0 : (NT - T0 > kTilesPerWave ? kTilesPerWave : NT - T0);
+    constexpr unsigned useA = wave_blocks(R, W, false) | wave_blocks(R, W, true);
+    constexpr unsigned useB = wave_blocks(R, W, true);
+    const int lane = tid & 63;
+
+    acc_t vre[kTilesPerWave], vim[kTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t) {
+        vre[t] = acc_t{};
+        vim[t] = acc_t{};
+    }
+
+    for (int kc0 = 0; kc0 < a.n_c; kc0 += C_::kKc) {
+        __syncthreads();
+        stage_chunk<MODE, R>(a, chan, lds, kc0, tid);
+        __syncthreads();
+        if constexpr (NW > 0) {
+#pragma unroll
+            for (int ks = 0; ks < C_::kSteps; ++ks) {
+                const int off = (lane & 31) * C_::kRowB + ks * 32 + (lane >> 5) * 16;
+                if constexpr (MODE == XM_FP16_SPLIT) {
+                    uintx4 fh[R], fl[R], gh[R], gl[R];
+                    static_for<R>([&](auto bi) {
+                        constexpr int b = decltype(bi)::value;
+                        if constexpr ((useA >> b) & 1u) {
+                            fh[b] = *(const uintx4*)(lds + b * 32 * C_::kRowB + off);
+                            fl[b] = *(const uintx4*)(lds + b * 32 * C_::kRowB + off + 128);
+                        }
+                        if constexpr ((useB >> b) & 1u) {
+                            gh[b] = swapneg_f16(fh[b]);
+                            gl[b] = swapneg_f16(fl[b]);
+                        }
+                    });
+                    // three products, each over all tiles: independent accumulators between
+                    // dependent MFMAs
+                    static_for<3>([&](auto pi) {
+                        constexpr int p = decltype(pi)::value;
+                        static_for<NW>([&](auto ti) {
+                            constexpr int t = decltype(ti)::value;
+                            constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
+                            const frag_t A = __builtin_bit_cast(frag_t, p == 2 ? fl[I] : fh[I]);
+                            const frag_t B = __builtin_bit_cast(frag_t, p == 1 ? fl[J] : fh[J]);
+                            const frag_t Bs = __builtin_bit_cast(frag_t, p == 1 ? gl[J] : gh[J]);
+                            vre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, vre[t], 0, 0, 0);
+                            vim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Bs, vim[t], 0, 0, 0);
+                        });
+                    });
+                } else {
+                    uintx4 f[R], g[R];
+                    static_for<R>([&](auto bi) {
+                        constexpr int b = decltype(bi)::value;
+                        if constexpr ((useA >> b) & 1u) f[b] = *(const uintx4*)(lds + b * 32 * C_::kRowB + off);
+                        if constexpr ((useB >> b) & 1u) g[b] = swapneg_i8(f[b]);
+                    });
+                    static_for<NW>([&](auto ti) {
+                        constexpr int t = decltype(ti)::value;
+                        constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
+                        const frag_t A = __builtin_bit_cast(frag_t, f[I]);
+                        const frag_t B = __builtin_bit_cast(frag_t, f[J]);
+                        const frag_t Bs = __builtin_bit_cast(frag_t, g[J]);
+                        vre[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B, vre[t], 0, 0, 0);
+                        vim[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, Bs, vim[t], 0, 0, 0);
+                    });
+                }
+            }
+        }
+    }
+
+    // ---- epilogue: stored baselines s1 >= s2, all four polarisation products ----
+    if constexpr (NW > 0) {
+        const int64_t ch = blockIdx.x;
+        const int64_t B = (int64_t)a.S * (a.S + 1) / 2;
+        static_for<NW>([&](auto ti) {
+            constexpr int t = decltype(ti)::value;
+            constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
+            const int b = 32 * J + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int aa = 32 * I + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (aa < a.M && b < a.M) {
+                    const int s1 = aa >> 1, s2 = b >> 1;
+                    if (s1 >= s2) {
+                        const int64_t idx = (ch * B + (int64_t)s1 * (s1 + 1) / 2 + s2) * 4 + 2 * (aa & 1) + (b & 1);
+                        if constexpr (MODE == XM_FP16_SPLIT) {
+                            const float re = vre[t][r] * a.out_scale;
+                            const float im = aa == b ? 0.f : vim[t][r] * a.out_scale;
+                            ((float2*)a.vis)[idx] = make_float2(re, im);
+                        } else {
+                            ((int2*)a.vis)[idx] = make_int2(vre[t][r], aa == b ? 0 : vim[t][r]);
+                        }
+                    }
+                }
+            }
+        });
+    }
+}
+
+template <int MODE, int R>
+__global__ __launch_bounds__(256) void xstage_mfma_kernel(XArgs a) {
+    using C_ = XCfg<MODE>;
+    __shared__ __attribute__((aligned(16))) char lds[R * 32 * C_::kRowB];
+    const int tid = threadIdx.x;
+    const char* chan = (const char*)a.chan + (int64_t)blockIdx.x * a.chan_stride;
+    switch (tid >> 6) {
+        case 0: xwave<MODE, R, 0>(a, chan, lds, tid); break;
+        case 1: xwave<MODE, R, 1>(a, chan, lds, tid); break;
+        case 2: xwave<MODE, R, 2>(a, chan, lds, tid); break;
+        default: xwave<MODE, R, 3>(a, chan, lds, tid); break;
+    }
+}
+
+template <int MODE>
+hipError_t launch_mode(const XArgs& a, hipStream_t st) {
+    const int R = (a.M + 31) / 32;
+    const dim3 grid((unsigned)a.n_chan), block(256);
+    switch (R) {
+        case 1: hipLaunchKernelGGL((xstage_mfma_kernel<MODE, 1>), grid, block, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((xstage_mfma_kernel<MODE, 2>), grid, block, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((xstage_mfma_kernel<MODE, 3>), grid, block, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((xstage_mfma_kernel<MODE, 4>), grid, block, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((xstage_mfma_kernel<MODE, 5>), grid, block, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ plain FP32 form ---
+constexpr int kF32Kc = 16;        // complex samples per LDS chunk
+
+__global__ __launch_bounds__(256) void xstage_fp32_kernel(XArgs a) {
+    extern __shared__ float2 zl[];                 // [kF32Kc][ls] with ls = 8*nb8 + 1
+    const int tid = threadIdx.x;
+    const int groups = (a.n_blocks8 * (a.n_blocks8 + 1) / 2 + 255) / 256;
+    const int64_t ch = blockIdx.x / groups;
+    const int g = blockIdx.x % groups;
+    const int rows = 8 * a.n_blocks8, ls = rows + 1;
+    const float2* __restrict__ z = (const float2*)((const char*)a.chan + ch * a.chan_stride);
+
+    // this thread's 8x8 block (A >= Bk) in the lower triangle of block rows
+    const int blk = g * 256 + tid;
+    const bool active = blk < a.n_blocks8 * (a.n_blocks8 + 1) / 2;
+    int A = 0, Bk = 0;
+    if (active) {
+        A = (int)((sqrtf(8.f * blk + 1.f) - 1.f) * 0.5f);
+        while (A * (A + 1) / 2 > blk) --A;
+        while ((A + 1) * (A + 2) / 2 <= blk) ++A;
+        Bk = blk - A * (A + 1) / 2;
+    }
+    float vr[8][8], vi[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) { vr[i][j] = 0.f; vi[i][j] = 0.f; }
+
+    for (int kc0 = 0; kc0 < a.n_c; kc0 += kF32Kc) {
+        __syncthreads();
+        for (int id = tid; id < rows * kF32Kc; id += 256) {
+            const int row = id / kF32Kc, k = id % kF32Kc, col = kc0 + k;
+            float2 v = make_float2(0.f, 0.f);
+            if (row < a.M && col < a.n_c) v = z[(int64_t)row * a.pitch + col];
+            zl[k * ls + row] = v;
+        }
+        __syncthreads();
+        if (active) {
+            for (int k = 0; k < kF32Kc; ++k) {
+                float2 xa[8], xb[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) { xa[i] = zl[k * ls + 8 * A + i]; xb[i] = zl[k * ls + 8 * Bk + i]; }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        vr[i][j] = fmaf(xa[i].x, xb[j].x, fmaf(xa[i].y, xb[j].y, vr[i][j]));
+                        vi[i][j] = fmaf(xa[i].y, xb[j].x, fmaf(-xa[i].x, xb[j].y, vi[i][j]));
+                    }
+            }
+        }
+    }
+    if (!active) return;
+    const int64_t B = (int64_t)a.S * (a.S + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int aa = 8 * A + i, b = 8 * Bk + j;
+            if (aa < a.M && b < a.M && (aa >> 1) >= (b >> 1)) {
+                const int s1 = aa >> 1, s2 = b >> 1;
+                const int64_t idx = (ch * B + (int64_t)s1 * (s1 + 1) / 2 + s2) * 4 + 2 * (aa & 1) + (b & 1);
+                ((float2*)a.vis)[idx] = make_float2(vr[i][j], aa == b ? 0.f : vi[i][j]);
+            }
+        }
+}
+
+}  // namespace
+
+hipError_t launch_xstage_mfma(int x_mode, const XArgs& a, hipStream_t st) {
+    if (a.n_chan <= 0) return hipSuccess;
+    if (x_mode == XM_FP16_SPLIT) return launch_mode<XM_FP16_SPLIT>(a, st);
+    if (x_mode == XM_INT8) return launch_mode<XM_INT8>(a, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_xstage_fp32(const XArgs& a, hipStream_t st) {
+    if (a.n_chan <= 0) return hipSuccess;
+    const int nblk = a.n_blocks8 * (a.n_blocks8 + 1) / 2;
+    const int groups = (nblk + 255) / 256;
+    const size_t lds = (size_t)kF32Kc * (8 * a.n_blocks8 + 1) * sizeof(float2);
+    hipLaunchKernelGGL(xstage_fp32_kernel, dim3((unsigned)((int64_t)a.n_chan * groups)), dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace cobalt

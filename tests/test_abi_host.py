@@ -1,0 +1,104 @@
+"""The C ABI on the host (no GPU): the library loads, exports every function the header
+declares, and validates settings with the documented error codes before touching a GPU."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1801_04834_amd import binding, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cobalt.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cobalt_[a-z_]+)\s*\(", txt)))
+
+
+def _lib():
+    if not os.path.exists(binding.lib_path):
+        pytest.skip("libcobalt.so not built (run __graft_entry__.build())")
+    return binding.load_library()
+
+
+def test_header_declares_the_binding_surface():
+    assert _declared() == sorted(binding.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert getattr(lib, name) is not None
+
+
+def _kw(**over):
+    w = synth.workload("int16_share")
+    kw = dict(n_stations=w.S, n_subbands=w.SB, samples_per_block=w.N, sample_type=w.sample_type,
+              x_mode=w.x_mode, fir=w.fir(), subband_freqs=w.subband_freqs(), bandpass=w.bandpass(),
+              fp16_prescale_log2=5, requant_gain=8.0)
+    kw.update(over)
+    return kw
+
+
+def test_estimate_bytes_of_the_16bit_share():
+    _lib()
+    n = binding.estimate_bytes(**_kw())
+    # channelised FP16 hi/lo planes dominate: 64 SB x 64 ch x 2 x 152 x 3072 x 4 B
+    chan = 64 * 64 * 2 * 152 * 3072 * 4
+    hist = 2 * 64 * 152 * 960 * 4          # two FIR-history buffers of (T-1)*C ci16 samples
+    assert chan + hist <= n <= chan + hist + 2**20
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(n_stations=0), binding.EINVAL),
+    (dict(n_pols=3), binding.EUNSUPPORTED),
+    (dict(n_subbands=0), binding.EINVAL),
+    (dict(n_channels=128), binding.EUNSUPPORTED),
+    (dict(n_taps=8), binding.EUNSUPPORTED),
+    (dict(samples_per_block=1000), binding.EINVAL),
+    (dict(samples_per_block=-64), binding.EINVAL),
+    (dict(sample_type=7), binding.EINVAL),
+    (dict(x_mode=9), binding.EINVAL),
+    (dict(sample_rate=0.0), binding.EINVAL),
+    (dict(n_stations=81), binding.EUNSUPPORTED),
+    (dict(n_stations=129, x_mode=synth.X_FP32), binding.EUNSUPPORTED),
+    (dict(x_mode=synth.X_INT8, requant_gain=0.0), binding.EINVAL),
+    (dict(x_mode=synth.X_INT8, samples_per_block=64 * 66592), binding.EOVERFLOW),
+    (dict(fp16_prescale_log2=30), binding.EINVAL),
+    (dict(fir=np.full(1024, np.nan, np.float32)), binding.EINVAL),
+    (dict(subband_freqs=np.full(64, np.inf)), binding.EINVAL),
+])
+def test_invalid_settings_return_codes(over, code):
+    _lib()
+    with pytest.raises(binding.CobaltError) as ei:
+        binding.estimate_bytes(**_kw(**over))
+    assert ei.value.code == code
+    assert binding.load_library().cobalt_last_error().decode()
+
+
+def test_int8_overflow_bound_edge():
+    _lib()
+    ok = binding.estimate_bytes(**_kw(x_mode=synth.X_INT8, samples_per_block=64 * 66572))
+    assert ok > 0
+    with pytest.raises(binding.CobaltError) as ei:
+        binding.estimate_bytes(**_kw(x_mode=synth.X_INT8, samples_per_block=64 * 66573))
+    assert ei.value.code == binding.EOVERFLOW
+
+
+def test_largest_mfma_setting_is_accepted():
+    _lib()
+    assert binding.estimate_bytes(**_kw(n_stations=80)) > 0
+    assert binding.estimate_bytes(**_kw(n_stations=128, x_mode=synth.X_FP32)) > 0
+    assert binding.estimate_bytes(**_kw(samples_per_block=0)) > 0
+
+
+def test_plan_requires_the_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "lib_path", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_LIB", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.load_library()
