@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--workload", default="int16_share", choices=["int16_share", "int8_full", "plain_fx"])
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 form (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-subbands", type=int, default=1, help="subbands in the oracle sample")
+    ap.add_argument("--cpu-subbands", type=int, default=2, help="subbands in the oracle sample")
     return ap.parse_args()
 
 
