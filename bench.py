@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--workload", default="int16_share", choices=["int16_share", "int8_full", "plain_fx"])
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 form (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-subbands", type=int, default=2, help="subbands in the oracle sample")
+    ap.add_argument("--cpu-subbands", type=int, default=6, help="subbands in the oracle sample")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -142,6 +144,20 @@ def main():
     delays = w.delays(0)
     torch.cuda.synchronize()
     log(f"bench: input {x.numel() * x.element_size() / 1e9:.2f} GB resident ({time.perf_counter() - t0:.1f} s)")
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * 2**20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy {n} B read + {n} B written in {e0.elapsed_time(e1):.3f} ms "
+            f"({2 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9:.1f} GB/s)")
+        del src, dst
 
     plan = binding.plan_for(w)
     info = plan.info

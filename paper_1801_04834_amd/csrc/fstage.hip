@@ -132,13 +132,27 @@ template <> struct Samp<ST_CF32> {
     static __device__ __forceinline__ float2 cvt(raw_t w) { return w; }
 };
 
-struct __attribute__((aligned(4))) half2_t { _Float16 x, y; };
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
 struct __attribute__((aligned(2))) char2_t { int8_t x, y; };
 
+template <int OM> struct OutFmt;
+template <> struct OutFmt<XM_FP32> { static constexpr int kPlanes = 1, kElem = 8; };
+template <> struct OutFmt<XM_FP16_SPLIT> { static constexpr int kPlanes = 2, kElem = 4; };
+template <> struct OutFmt<XM_INT8> { static constexpr int kPlanes = 1, kElem = 2; };
+
+// exp(2 pi i r) for a phase r already reduced to [-1/2, 1/2] cycles (hardware sin/cos take
+// the argument in revolutions)
+__device__ __forceinline__ float2 phasor_rev(double cyc) {
+    const float r = (float)(cyc - rint(cyc));
+    return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+}
+
 template <int ST, int OM>
-__global__ __launch_bounds__(64) void fstage_kernel(FArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fstage_kernel(FArgs a) {
     using S_ = Samp<ST>;
     using raw_t = typename S_::raw_t;
+    using O_ = OutFmt<OM>;
     __shared__ float2 ylds[kPass * kRowF2];
 
     const int lane = threadIdx.x;
@@ -147,8 +161,13 @@ __global__ __launch_bounds__(64) void fstage_kernel(FArgs a) {
     const int sb = (int)(st % a.SB);
     const int row_in = (int)(st / a.SB);                                 // input index s*P + p
     const int s = row_in >> 1;
+    // wave-uniform bases; per-lane offsets below stay within 2^31 bytes
     const raw_t* __restrict__ in = (const raw_t*)a.in + st * a.N;
     const raw_t* __restrict__ hold = (const raw_t*)a.hist_old + st * kHist;
+    char* __restrict__ out = (char*)a.out + ((int64_t)sb * kC * O_::kPlanes * a.M + row_in) * a.pitch * O_::kElem;
+    const uint32_t cstride = (uint32_t)(O_::kPlanes * a.M * a.pitch * O_::kElem);   // bytes between channels
+    const uint32_t pstride = (uint32_t)(a.M * a.pitch * O_::kElem);                  // bytes between planes
+    const uint32_t ulane = (uint32_t)lane;
 
     // The last chunk of every stream writes the history for the next block: the final
     // (T-1)*C samples of [old history, block].
@@ -171,40 +190,50 @@ __global__ __launch_bounds__(64) void fstage_kernel(FArgs a) {
     const double fsb = a.f_sb[sb];
     const int jj = lane >> 1, hh = lane & 1;
 
-    auto load_row = [&](int r) -> raw_t {      // r is wave-uniform
-        if (r < 0) return hold[(r + kHistRows) * kC + lane];
-        if (r < a.n_c) return in[(int64_t)r * kC + lane];
-        return raw_t{};
-    };
-
     const int j0 = chunk * kChunk;
     const int jend = min(j0 + kChunk, a.pitch);
 
-    float2 tail[kHistRows];
+    raw_t tail[kHistRows];                     // raw samples of the 15 rows before the pass
+    if (j0 >= kHistRows && j0 <= a.n_c) {
 #pragma unroll
-    for (int i = 0; i < kHistRows; ++i) tail[i] = S_::cvt(load_row(j0 - kHistRows + i));
+        for (int i = 0; i < kHistRows; ++i) tail[i] = in[(uint32_t)((j0 - kHistRows + i) * kC) + ulane];
+    } else {
+#pragma unroll
+        for (int i = 0; i < kHistRows; ++i) {
+            const int r = j0 - kHistRows + i;  // wave-uniform
+            tail[i] = r < 0 ? hold[(r + kHistRows) * kC + lane] : r < a.n_c ? in[r * kC + lane] : raw_t{};
+        }
+    }
 
     for (int jb = j0; jb < jend; jb += kPass) {
         raw_t nw[kPass];
+        if (jb + kPass <= a.n_c) {
 #pragma unroll
-        for (int r = 0; r < kPass; ++r) nw[r] = load_row(jb + r);
+            for (int r = 0; r < kPass; ++r) nw[r] = in[(uint32_t)((jb + r) * kC) + ulane];
+        } else {
+#pragma unroll
+            for (int r = 0; r < kPass; ++r) nw[r] = jb + r < a.n_c ? in[(uint32_t)((jb + r) * kC) + ulane] : raw_t{};
+        }
 
         // ---- polyphase FIR: y_j[p] = sum_t h[t*C + p] x[(j - T + 1 + t)*C + p] ----
+        // input-stationary: window row w feeds outputs j = w - t (taps in ascending t)
         float2 acc[kPass];
 #pragma unroll
-        for (int j = 0; j < kPass; ++j) {
-            float yr = 0.f, yi = 0.f;
+        for (int j = 0; j < kPass; ++j) acc[j] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int w = 0; w < kPass + kHistRows; ++w) {
+            const float2 x = S_::cvt(w < kHistRows ? tail[w] : nw[w - kHistRows]);
 #pragma unroll
             for (int t = 0; t < kT; ++t) {
-                const int w = j + t;             // window row: < 15 from the tail
-                const float2 x = w < kHistRows ? tail[w] : S_::cvt(nw[w - kHistRows]);
-                yr = fmaf(h[t], x.x, yr);
-                yi = fmaf(h[t], x.y, yi);
+                const int j = w - t;
+                if (j >= 0 && j < kPass) {
+                    acc[j].x = fmaf(h[t], x.x, acc[j].x);
+                    acc[j].y = fmaf(h[t], x.y, acc[j].y);
+                }
             }
-            acc[j] = make_float2(yr, yi);
         }
 #pragma unroll
-        for (int i = 0; i < kHistRows; ++i) tail[i] = S_::cvt(nw[kPass - kHistRows + i]);
+        for (int i = 0; i < kHistRows; ++i) tail[i] = nw[kPass - kHistRows + i];
 
         // ---- first DIF stage across lanes p, p+32 (two channel samples per swap) ----
 #pragma unroll
@@ -234,50 +263,54 @@ __global__ __launch_bounds__(64) void fstage_kernel(FArgs a) {
         __syncthreads();
         fft32(xr, xi);
 
-        // ---- fine delay + bandpass, then write channel rows ----
+        // ---- fine delay + bandpass, then write channel rows in ascending channel order ----
+        // This lane holds channel c = 2q + hh (q = 0..31) of channel sample j; its phase in
+        // cycles is f_c tau(j) = tau(j) (f_SB + (c - C/2) df), linear in q.  Exact phasors
+        // (FP64 argument and reduction) every 4 steps of q, complex recurrence in between.
         const int j = jb + jj;
         const bool live = j < a.n_c;
         const double tau = tau0 + (tau1 - tau0) * (double)j / (double)a.n_c;
-        const double c1 = tau * a.df;                  // cycles per channel step
-        const double c0 = fma((double)hh, c1, tau * fsb);
+        const double c1 = tau * a.df;                                  // cycles per channel
+        const double c0 = fma((double)(hh - kC / 2), c1, tau * fsb);   // cycles at q = 0
+        const float2 step = phasor_rev(2.0 * c1);                      // q -> q + 1
+        float2 ph = make_float2(1.f, 0.f);
+        const uint32_t lane_off = (uint32_t)hh * cstride + (uint32_t)((jb + jj) * O_::kElem);
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            const int m = bitrev5(i);                  // this register holds bin 2m + hh
-            const int m2 = 2 * m - (m >= 16 ? 64 : 0); // signed bin offset minus hh
-            const int c_even = (2 * m + 32) & 63;
-            const double cyc = fma((double)m2, c1, c0);
-            const float r = (float)(cyc - rint(cyc));
-            const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
-            const float b = hh ? a.bscale[c_even + 1] : a.bscale[c_even];
-            const float pr_ = cs * b, pi_ = sn * b;
+        for (int q = 0; q < 32; ++q) {
+            if (q % 4 == 0) {
+                ph = phasor_rev(fma((double)(2 * q), c1, c0));
+            } else {
+                const float pr_ = ph.x * step.x - ph.y * step.y;
+                ph.y = ph.x * step.y + ph.y * step.x;
+                ph.x = pr_;
+            }
+            const int m = (q + 16) & 31;               // FFT bin 2m + hh is channel 2q + hh
+            const int i = bitrev5(m);                  // register holding bin m
+            const float b = hh ? a.bscale[2 * q + 1] : a.bscale[2 * q];
+            const float pr_ = ph.x * b, pi_ = ph.y * b;
             float zr = xr[i] * pr_ - xi[i] * pi_;
             float zi = xr[i] * pi_ + xi[i] * pr_;
             if (!live) { zr = 0.f; zi = 0.f; }
-            const int c = c_even + hh;
-            const int64_t ch = (int64_t)sb * kC + c;
+            const uint32_t o = lane_off + (uint32_t)(2 * q) * cstride;
+            char* dst = out + o;
             if constexpr (OM == XM_FP32) {
-                float2* out = (float2*)a.out;
-                out[(ch * a.M + row_in) * a.pitch + j] = make_float2(zr, zi);
+                *(float2*)dst = make_float2(zr, zi);
             } else if constexpr (OM == XM_FP16_SPLIT) {
-                half2_t hi, lo;
-                hi.x = (_Float16)zr;
-                hi.y = (_Float16)zi;
-                lo.x = (_Float16)(zr - (float)hi.x);
-                lo.y = (_Float16)(zi - (float)hi.y);
-                half2_t* out = (half2_t*)a.out;
-                const int64_t plane = (int64_t)a.M * a.pitch;
-                const int64_t base = ch * 2 * plane + (int64_t)row_in * a.pitch + j;
-                out[base] = hi;
-                out[base + plane] = lo;
+                // hi = fp16(z) (round to nearest even), lo = fp16(z - hi)
+                const float2v z2 = {zr, zi};
+                const half2v hi = __builtin_convertvector(z2, half2v);
+                const half2v lo = __builtin_convertvector(z2 - __builtin_convertvector(hi, float2v), half2v);
+                *(half2v*)dst = hi;
+                *(half2v*)(out + (o + pstride)) = lo;
             } else {
                 const float qr = fminf(fmaxf(rintf(zr), -127.f), 127.f);
                 const float qi = fminf(fmaxf(rintf(zi), -127.f), 127.f);
                 char2_t v;
                 v.x = (int8_t)(int)qr;
                 v.y = (int8_t)(int)qi;
-                char2_t* out = (char2_t*)a.out;
-                out[(ch * a.M + row_in) * a.pitch + j] = v;
+                *(char2_t*)dst = v;
             }
+            if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound live ranges per 4 channels
         }
     }
 }

@@ -95,48 +95,69 @@ __device__ __forceinline__ uintx4 swapneg_i8(uintx4 d) {
     return r;
 }
 
-// Stage one K chunk of all R*32 rows into LDS (rows >= M and columns >= N_c are zero).
+// One K chunk of all R*32 rows, staged global -> registers -> LDS.  Each thread owns
+// kPieces 16-byte pieces; rows >= M and columns >= N_c are zero.  The loads for the next
+// chunk are issued before the MFMAs of the current one, so HBM latency hides behind them.
 template <int MODE, int R>
-__device__ __forceinline__ void stage_chunk(const XArgs& a, const char* __restrict__ chan, char* lds, int kc0, int tid) {
-    using C_ = XCfg<MODE>;
-    if constexpr (MODE == XM_FP16_SPLIT) {
-        const int64_t plane = (int64_t)a.M * a.pitch * 4;
-        for (int id = tid; id < R * 32 * 16; id += 256) {
-            const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
-            const int col0 = kc0 + seg * 4;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (row < a.M) {
-                v = *(const uint4*)(chan + pl * plane + ((int64_t)row * a.pitch + col0) * 4);
-                if (col0 + 0 >= a.n_c) v.x = 0;
-                if (col0 + 1 >= a.n_c) v.y = 0;
-                if (col0 + 2 >= a.n_c) v.z = 0;
-                if (col0 + 3 >= a.n_c) v.w = 0;
-            }
-            *(uint4*)(lds + row * C_::kRowB + pl * 128 + seg * 16) = v;
-        }
-    } else {
-        for (int id = tid; id < R * 32 * 8; id += 256) {
-            const int row = id >> 3, seg = id & 7;
-            const int col0 = kc0 + seg * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (row < a.M && col0 < a.pitch) {
-                v = *(const uint4*)(chan + ((int64_t)row * a.pitch + col0) * 2);
-                const int keep = a.n_c - col0;                 // complex samples to keep
-                if (keep < 8) {
-                    unsigned w[4] = {v.x, v.y, v.z, v.w};
+struct Stage {
+    static constexpr int kPieces = MODE == XM_FP16_SPLIT ? R * 32 * 16 / 256 : R * 32 * 8 / 256;
+    uint4 v[kPieces > 0 ? kPieces : 1];
+
+    __device__ __forceinline__ void load(const XArgs& a, const char* __restrict__ chan, int kc0, int tid) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int k0 = 2 * e;                  // two char2 per dword
-                        if (k0 >= keep) w[e] = 0;
-                        else if (k0 + 1 >= keep) w[e] &= 0x0000ffffu;
+        for (int i = 0; i < kPieces; ++i) {
+            const int id = tid + 256 * i;
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if constexpr (MODE == XM_FP16_SPLIT) {
+                const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
+                const int col0 = kc0 + seg * 4;
+                if (row < a.M) {
+                    const int64_t plane = (int64_t)a.M * a.pitch * 4;
+                    x = *(const uint4*)(chan + pl * plane + ((int64_t)row * a.pitch + col0) * 4);
+                    if (col0 + 4 > a.n_c) {
+                        if (col0 + 0 >= a.n_c) x.x = 0;
+                        if (col0 + 1 >= a.n_c) x.y = 0;
+                        if (col0 + 2 >= a.n_c) x.z = 0;
+                        if (col0 + 3 >= a.n_c) x.w = 0;
                     }
-                    v = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            } else {
+                const int row = id >> 3, seg = id & 7;
+                const int col0 = kc0 + seg * 8;
+                if (row < a.M && col0 < a.pitch) {
+                    x = *(const uint4*)(chan + ((int64_t)row * a.pitch + col0) * 2);
+                    const int keep = a.n_c - col0;             // complex samples to keep
+                    if (keep < 8) {
+                        unsigned w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int k0 = 2 * e;              // two char2 per dword
+                            if (k0 >= keep) w[e] = 0;
+                            else if (k0 + 1 >= keep) w[e] &= 0x0000ffffu;
+                        }
+                        x = make_uint4(w[0], w[1], w[2], w[3]);
+                    }
                 }
             }
-            *(uint4*)(lds + row * C_::kRowB + seg * 16) = v;
+            v[i] = x;
         }
     }
-}
+
+    __device__ __forceinline__ void store(char* lds, int tid) const {
+        using C_ = XCfg<MODE>;
+#pragma unroll
+        for (int i = 0; i < kPieces; ++i) {
+            const int id = tid + 256 * i;
+            if constexpr (MODE == XM_FP16_SPLIT) {
+                const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
+                *(uint4*)(lds + row * C_::kRowB + pl * 128 + seg * 16) = v[i];
+            } else {
+                const int row = id >> 3, seg = id & 7;
+                *(uint4*)(lds + row * C_::kRowB + seg * 16) = v[i];
+            }
+        }
+    }
+};
 
 template <int MODE, int R, int W>
 __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ chan, char* lds, int tid) {
@@ -157,10 +178,13 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
         vim[t] = acc_t{};
     }
 
+    Stage<MODE, R> stage;
+    if (a.n_c > 0) stage.load(a, chan, 0, tid);
     for (int kc0 = 0; kc0 < a.n_c; kc0 += C_::kKc) {
+        __syncthreads();                                   // LDS free: previous chunk consumed
+        stage.store(lds, tid);
         __syncthreads();
-        stage_chunk<MODE, R>(a, chan, lds, kc0, tid);
-        __syncthreads();
+        if (kc0 + C_::kKc < a.n_c) stage.load(a, chan, kc0 + C_::kKc, tid);
         if constexpr (NW > 0) {
 #pragma unroll
             for (int ks = 0; ks < C_::kSteps; ++ks) {
@@ -243,7 +267,7 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
 }
 
 template <int MODE, int R>
-__global__ __launch_bounds__(256) void xstage_mfma_kernel(XArgs a) {
+__global__ __launch_bounds__(256, 2) void xstage_mfma_kernel(XArgs a) {
     using C_ = XCfg<MODE>;
     __shared__ __attribute__((aligned(16))) char lds[R * 32 * C_::kRowB];
     const int tid = threadIdx.x;
