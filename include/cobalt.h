@@ -32,12 +32,17 @@
  * ---------------------------------------
  *  input block   [S][P][SB][N] complex samples: int8 pairs (COBALT_CI8), int16 pairs
  *                (COBALT_CI16) or float pairs (COBALT_CF32), (re, im) interleaved.
- *  channelised   per channel (sb*C + c), planes x M rows x pitch channel samples:
- *                 FP32 mode      [SB][C][M][pitch] float (re, im)
- *                 FP16-split     [SB][C][2][M][pitch] _Float16 (re, im); plane 0 = hi,
+ *  channelised   K-blocked, per channel (sb*C + c): n_kb = pitch/32 blocks of 32 channel
+ *                samples, each block holding planes x M rows x 32 samples:
+ *                 FP32 mode      [SB][C][n_kb][M][32] float (re, im)
+ *                 FP16-split     [SB][C][n_kb][2][M][32] _Float16 (re, im); plane 0 = hi,
  *                                plane 1 = lo, hi + lo = 2^k * Z (k = fp16_prescale_log2)
- *                 INT8 mode      [SB][C][M][pitch] int8 (re, im)
- *                pitch = N_c rounded up to a multiple of 32; columns >= N_c are zero.
+ *                 INT8 mode      [SB][C][n_kb][M][32] int8 (re, im), values in [-127, 127]
+ *                Sample j of input row a sits in block j/32 at position j%32.  pitch = N_c
+ *                rounded up to a multiple of 32; positions j >= N_c are written as zero by
+ *                the F stage and ignored by the X stage.  One channel's K block is one
+ *                contiguous run (the X stage streams it; the F stage writes neighbouring
+ *                rows of it from concurrent waves).
  *  visibilities  [SB][C][B][4] complex: float (re, im) in FP32 / FP16-split modes,
  *                int32 (re, im) raw integer sums in INT8 mode.  Baseline index
  *                b(s1, s2) = s1(s1+1)/2 + s2 for s1 >= s2; pol pair q = 2*p1 + p2

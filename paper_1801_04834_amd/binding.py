@@ -173,10 +173,15 @@ class Plan:
         return {X_FP32: t.float32, X_FP16_SPLIT: t.float16, X_INT8: t.int8}[self.x_mode]
 
     @property
+    def n_kb(self):
+        return self.pitch // 32
+
+    @property
     def chan_shape(self):
+        """K-blocked: [SB][C][n_kb]([2 planes])[M][32][re, im]."""
         if self.x_mode == X_FP16_SPLIT:
-            return (self.SB, self.C, 2, self.M, self.pitch, 2)
-        return (self.SB, self.C, self.M, self.pitch, 2)
+            return (self.SB, self.C, self.n_kb, 2, self.M, 32, 2)
+        return (self.SB, self.C, self.n_kb, self.M, 32, 2)
 
     @property
     def vis_dtype(self):

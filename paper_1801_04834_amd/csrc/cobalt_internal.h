@@ -13,7 +13,8 @@ constexpr int kC = 64;
 constexpr int kT = 16;
 constexpr int kHistRows = kT - 1;              // FIR history in rows of C samples
 constexpr int kHist = kHistRows * kC;          // 960 samples carried per input stream
-constexpr int kPitchAlign = 32;                // channelised rows padded to 32 samples
+constexpr int kKBlock = 32;                    // channel samples per K block of the channelised layout
+constexpr int kPitchAlign = kKBlock;           // channelised rows padded to whole K blocks
 constexpr int kMaxMfmaInputs = 160;            // 5 row blocks of 32 (80 stations)
 constexpr int kMaxFp32Inputs = 256;
 constexpr int kFChunk = 256;                  // channel samples per F-stage workgroup
@@ -25,13 +26,13 @@ struct FArgs {
     const void* in;          // [S][P][SB][N] samples
     const void* hist_old;    // [S*P*SB][kHist] samples, stream order (s*P + p)*SB + sb
     void* hist_new;          // same layout, written by the last chunk of each stream
-    void* out;               // channelised buffer (layout per mode, see cobalt.h)
+    void* out;               // channelised buffer, K-blocked (see cobalt.h)
     const float* fir;        // [kT * kC]
     const float* bscale;     // [kC] bandpass * mode scale (2^k or requant gain)
     const double* f_sb;      // [SB] subband sky centre frequency (Hz)
     const double* delays;    // [S][2] residual delay (s) at block start / end
     int64_t N;               // samples per block per stream
-    int32_t S, SB, M, n_c, pitch, n_chunks;
+    int32_t S, SB, M, n_c, pitch, n_chunks, n_kb;
     double df;               // channel width f_s / C (Hz)
 };
 
@@ -39,7 +40,7 @@ struct XArgs {
     const void* chan;        // channelised buffer
     void* vis;               // [SB*C][B][4] complex
     int64_t chan_stride;     // bytes per channel in the channelised buffer
-    int32_t M, S, n_c, pitch, n_chan, n_blocks8;
+    int32_t M, S, n_c, pitch, n_chan, n_blocks8, n_kb;
     float out_scale;         // FP16-split: 2^-2k
 };
 

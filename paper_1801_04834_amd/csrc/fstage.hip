@@ -26,7 +26,8 @@
 namespace cobalt {
 namespace {
 
-constexpr int kPass = 32;                 // channel samples per pass
+constexpr int kPass = 32;                 // channel samples per pass (= one K block)
+static_assert(kPass == kKBlock, "a pass writes exactly one K block per channel");
 constexpr int kChunk = kFChunk;           // channel samples per workgroup (8 passes)
 constexpr int kRowF2 = 68;                // LDS row: two 32-point halves, 16 B apart
 constexpr int kHalfF2 = 34;
@@ -156,17 +157,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fs
     __shared__ float2 ylds[kPass * kRowF2];
 
     const int lane = threadIdx.x;
-    const int chunk = (int)(blockIdx.x % (unsigned)a.n_chunks);
-    const int64_t st = (int64_t)(blockIdx.x / (unsigned)a.n_chunks);   // (s*P + p)*SB + sb
-    const int sb = (int)(st % a.SB);
-    const int row_in = (int)(st / a.SB);                                 // input index s*P + p
+    // grid order: input row fastest, so neighbouring rows of one channel K block are
+    // written by concurrently running waves (contiguous in the K-blocked layout)
+    const int row_in = (int)(blockIdx.x % (unsigned)a.M);               // input index s*P + p
+    const int rest = (int)(blockIdx.x / (unsigned)a.M);
+    const int chunk = rest % a.n_chunks;
+    const int sb = rest / a.n_chunks;
+    const int64_t st = (int64_t)row_in * a.SB + sb;                      // input stream (s*P + p)*SB + sb
     const int s = row_in >> 1;
     // wave-uniform bases; per-lane offsets below stay within 2^31 bytes
     const raw_t* __restrict__ in = (const raw_t*)a.in + st * a.N;
     const raw_t* __restrict__ hold = (const raw_t*)a.hist_old + st * kHist;
-    char* __restrict__ out = (char*)a.out + ((int64_t)sb * kC * O_::kPlanes * a.M + row_in) * a.pitch * O_::kElem;
-    const uint32_t cstride = (uint32_t)(O_::kPlanes * a.M * a.pitch * O_::kElem);   // bytes between channels
-    const uint32_t pstride = (uint32_t)(a.M * a.pitch * O_::kElem);                  // bytes between planes
+    // channelised layout [SB][C][n_kb][planes][M][32]: element (row, j) of channel c lives
+    // in K block j/32 at position j%32 of the row
+    char* __restrict__ out = (char*)a.out + ((int64_t)sb * kC * a.n_kb * O_::kPlanes * a.M + row_in) * kKBlock * O_::kElem;
+    const uint32_t cstride = (uint32_t)(a.n_kb * O_::kPlanes * a.M * kKBlock * O_::kElem);   // bytes between channels
+    const uint32_t pstride = (uint32_t)(a.M * kKBlock * O_::kElem);                          // bytes between planes
+    const uint32_t kbstride = (uint32_t)(O_::kPlanes * a.M * kKBlock * O_::kElem);           // bytes between K blocks
     const uint32_t ulane = (uint32_t)lane;
 
     // The last chunk of every stream writes the history for the next block: the final
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fs
         const double c0 = fma((double)(hh - kC / 2), c1, tau * fsb);   // cycles at q = 0
         const float2 step = phasor_rev(2.0 * c1);                      // q -> q + 1
         float2 ph = make_float2(1.f, 0.f);
-        const uint32_t lane_off = (uint32_t)hh * cstride + (uint32_t)((jb + jj) * O_::kElem);
+        const uint32_t lane_off = (uint32_t)hh * cstride + (uint32_t)(jb / kKBlock) * kbstride + (uint32_t)(jj * O_::kElem);
 #pragma unroll
         for (int q = 0; q < 32; ++q) {
             if (q % 4 == 0) {
@@ -324,7 +331,7 @@ __global__ void zero_fill_kernel(uint4* p, int64_t n16, uint8_t* tail, int64_t n
 
 template <int ST>
 hipError_t launch_st(int x_mode, const FArgs& a, int n_streams, hipStream_t st) {
-    const dim3 grid((unsigned)((int64_t)n_streams * a.n_chunks)), block(64);
+    const dim3 grid((unsigned)((int64_t)n_streams * a.n_chunks)), block(64);   // = SB * n_chunks * M
     switch (x_mode) {
         case XM_FP32: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP32>), grid, block, 0, st, a); break;
         case XM_FP16_SPLIT: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP16_SPLIT>), grid, block, 0, st, a); break;

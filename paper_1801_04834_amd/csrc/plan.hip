@@ -97,6 +97,14 @@ int validate(const cobalt_config* c, Sizes* z) {
         return fail(COBALT_EINVAL, "fp16_prescale_log2 must lie in [-24, 24]");
 
     s.sample_bytes = c->sample_type == COBALT_CI8 ? 2 : c->sample_type == COBALT_CI16 ? 4 : 8;
+    {
+        // kernels address one input stream and one subband's channelised data with 32-bit
+        // byte offsets
+        const int64_t elem = c->x_mode == COBALT_X_INT8 ? 2 : c->x_mode == COBALT_X_FP16_SPLIT ? 4 : 8;
+        const int64_t planes = c->x_mode == COBALT_X_FP16_SPLIT ? 2 : 1;
+        if (s.N * s.sample_bytes >= ((int64_t)1 << 31) || (int64_t)kC * planes * s.M * s.pitch * elem >= ((int64_t)1 << 31))
+            return fail(COBALT_EUNSUPPORTED, "block too long: one subband's channelised data must stay below 2 GiB");
+    }
     s.input_bytes = s.streams * s.N * s.sample_bytes;
     s.chan_elem_bytes = c->x_mode == COBALT_X_INT8 ? 2 : c->x_mode == COBALT_X_FP16_SPLIT ? 4 : 8;
     s.chan_planes = c->x_mode == COBALT_X_FP16_SPLIT ? 2 : 1;
@@ -222,6 +230,7 @@ int run_fstage(cobalt_plan* p, const void* d_in, const double* d_delays, void* d
     a.n_c = (int)z.n_c;
     a.pitch = (int)z.pitch;
     a.n_chunks = (int)((z.pitch + kFChunk - 1) / kFChunk);
+    a.n_kb = (int)(z.pitch / kKBlock);
     a.df = p->cfg.sample_rate_hz / kC;
     hipError_t e = launch_fstage(p->cfg.sample_type, p->cfg.x_mode, a, (int)z.streams, st);
     if (e != hipSuccess) return hip_fail(e, "F-stage launch");
@@ -241,6 +250,7 @@ int run_xstage(cobalt_plan* p, const void* d_chan, void* d_vis, hipStream_t st) 
     a.pitch = (int)z.pitch;
     a.n_chan = (int)(z.SB * kC);
     a.n_blocks8 = (int)((z.M + 7) / 8);
+    a.n_kb = (int)(z.pitch / kKBlock);
     a.out_scale = std::ldexp(1.0f, -2 * p->cfg.fp16_prescale_log2);
     hipError_t e = p->cfg.x_mode == COBALT_X_FP32 ? launch_xstage_fp32(a, st) : launch_xstage_mfma(p->cfg.x_mode, a, st);
     if (e != hipSuccess) return hip_fail(e, "X-stage launch");

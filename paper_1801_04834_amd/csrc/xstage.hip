@@ -112,8 +112,9 @@ struct Stage {
                 const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
                 const int col0 = kc0 + seg * 4;
                 if (row < a.M) {
-                    const int64_t plane = (int64_t)a.M * a.pitch * 4;
-                    x = *(const uint4*)(chan + pl * plane + ((int64_t)row * a.pitch + col0) * 4);
+                    // K block kc0/32: [hi: M rows x 128 B][lo: M rows x 128 B], contiguous
+                    const char* blk = chan + (int64_t)(kc0 / kKBlock) * (2 * a.M * 128);
+                    x = *(const uint4*)(blk + pl * (a.M * 128) + row * 128 + seg * 16);
                     if (col0 + 4 > a.n_c) {
                         if (col0 + 0 >= a.n_c) x.x = 0;
                         if (col0 + 1 >= a.n_c) x.y = 0;
@@ -124,8 +125,9 @@ struct Stage {
             } else {
                 const int row = id >> 3, seg = id & 7;
                 const int col0 = kc0 + seg * 8;
-                if (row < a.M && col0 < a.pitch) {
-                    x = *(const uint4*)(chan + ((int64_t)row * a.pitch + col0) * 2);
+                const int kb = kc0 / kKBlock + (seg >> 2);      // two K blocks of 64 B rows
+                if (row < a.M && kb < a.n_kb) {
+                    x = *(const uint4*)(chan + (int64_t)kb * (a.M * 64) + row * 64 + (seg & 3) * 16);
                     const int keep = a.n_c - col0;             // complex samples to keep
                     if (keep < 8) {
                         unsigned w[4] = {x.x, x.y, x.z, x.w};
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(256) void xstage_fp32_kernel(XArgs a) {
         for (int id = tid; id < rows * kF32Kc; id += 256) {
             const int row = id / kF32Kc, k = id % kF32Kc, col = kc0 + k;
             float2 v = make_float2(0.f, 0.f);
-            if (row < a.M && col < a.n_c) v = z[(int64_t)row * a.pitch + col];
+            if (row < a.M && col < a.n_c) v = z[((int64_t)(col / kKBlock) * a.M + row) * kKBlock + (col % kKBlock)];
             zl[k * ls + row] = v;
         }
         __syncthreads();

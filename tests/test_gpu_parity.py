@@ -21,6 +21,7 @@ import pytest
 
 import oracle
 from paper_1801_04834_amd import synth
+from tests.layout import block, block_planes, unblock, unblock_planes
 from tests.metrics import coherence_error, frobenius_rel, near_rounding_boundary, vis_complex
 
 torch = pytest.importorskip("torch")
@@ -65,15 +66,21 @@ def _oracle_run(w, blocks):
     return outs
 
 
-def _chan_complex(plan, chan):
+def _chan_rows(plan, chan):
+    """Channelised tensor -> row-major numpy [SB, C, M, pitch, 2] (FP16: (hi, lo))."""
     c = chan.cpu().numpy()
     if plan.x_mode == synth.X_FP16_SPLIT:
+        return unblock_planes(c)
+    return unblock(c)
+
+
+def _chan_complex(plan, chan):
+    r = _chan_rows(plan, chan)
+    if plan.x_mode == synth.X_FP16_SPLIT:
         k = plan.kw.get("fp16_prescale_log2", 0)
-        hi = c[:, :, 0].astype(np.float64)
-        lo = c[:, :, 1].astype(np.float64)
-        v = (hi + lo) * 2.0 ** (-k)
+        v = (r[0].astype(np.float64) + r[1].astype(np.float64)) * 2.0 ** (-k)
     else:
-        v = c.astype(np.float64)
+        v = r.astype(np.float64)
     return (v[..., 0] + 1j * v[..., 1])[..., :plan.n_c]
 
 
@@ -119,13 +126,13 @@ def test_channelize_matches_oracle_two_blocks(st, mode, n_c):
         for k in range(2):
             chan = plan.channelize(_to_dev(blocks[k]), w.delays(k))
             torch.cuda.synchronize()
-            c = chan.cpu().numpy()
+            rows = _chan_rows(plan, chan)
             if plan.x_mode == synth.X_INT8:
-                assert np.all(c[..., plan.n_c:, :] == 0)
-                _check_int8_chan(c[..., :plan.n_c, :], outs[k], w.gain(), f"block {k}")
+                assert np.all(rows[..., plan.n_c:, :] == 0)
+                _check_int8_chan(rows[..., :plan.n_c, :], outs[k], w.gain(), f"block {k}")
             else:
-                pad = c[..., plan.n_c:, :]
-                assert np.all(pad == 0)
+                for r in (rows if plan.x_mode == synth.X_FP16_SPLIT else (rows,)):
+                    assert np.all(r[..., plan.n_c:, :] == 0)
                 _check_chan_float(_chan_complex(plan, chan), outs[k]["Z"], f"block {k}")
 
 
@@ -138,7 +145,7 @@ def test_x_int8_bit_exact(S, n_c):
     w = _small(S=S, SB=1, n_c=n_c, st=synth.CI8, mode=synth.X_INT8)
     with b.plan_for(w) as plan:
         q = synth.int8_channelised(seed=S * 1000 + n_c, n_chan=64, M=2 * S, n_c=n_c, pitch=plan.pitch)
-        chan = _to_dev(q.reshape(plan.chan_shape))
+        chan = _to_dev(block(q).reshape(plan.chan_shape))
         V = plan.correlate_channelized(chan)
         torch.cuda.synchronize()
         ref = oracle.correlate_int(q[:, :, :n_c, :], S)              # [64, B, 4, 2]
@@ -154,7 +161,7 @@ def test_x_int8_overflow_bound_extremes():
     w = _small(S=S, SB=1, n_c=n_c, st=synth.CI8, mode=synth.X_INT8)
     with b.plan_for(w) as plan:
         q = synth.int8_channelised(seed=3, n_chan=64, M=2 * S, n_c=n_c, pitch=plan.pitch, extreme=True)
-        V = plan.correlate_channelized(_to_dev(q.reshape(plan.chan_shape)))
+        V = plan.correlate_channelized(_to_dev(block(q).reshape(plan.chan_shape)))
         torch.cuda.synchronize()
         ref = oracle.correlate_int(q[:, :, :n_c, :], S)
         got = V.cpu().numpy().reshape(ref.shape).astype(np.int64)
@@ -174,9 +181,11 @@ def test_x_fp16_split_matches_oracle(S, n_c):
         zs = np.stack([Z.real, Z.imag], -1) * 2.0 ** k
         hi = zs.astype(np.float16)
         lo = (zs - hi.astype(np.float64)).astype(np.float16)
-        planes = np.zeros((64, 2, 2 * S, plan.pitch, 2), np.float16)
-        planes[:, 0, :, :n_c] = hi
-        planes[:, 1, :, :n_c] = lo
+        hip_ = np.zeros((64, 2 * S, plan.pitch, 2), np.float16)
+        lop_ = np.zeros((64, 2 * S, plan.pitch, 2), np.float16)
+        hip_[:, :, :n_c] = hi
+        lop_[:, :, :n_c] = lo
+        planes = block_planes(hip_, lop_)
         exact = (hi.astype(np.float64) + lo.astype(np.float64)) * 2.0 ** (-k)
         Zx = exact[..., 0] + 1j * exact[..., 1]
         V = plan.correlate_channelized(_to_dev(planes.reshape(plan.chan_shape)))
@@ -198,7 +207,7 @@ def test_x_fp32_matches_oracle(S, n_c):
         buf = np.zeros((64, 2 * S, plan.pitch, 2), np.float32)
         buf[:, :, :n_c, 0] = Z.real
         buf[:, :, :n_c, 1] = Z.imag
-        V = plan.correlate_channelized(_to_dev(buf.reshape(plan.chan_shape)))
+        V = plan.correlate_channelized(_to_dev(block(buf).reshape(plan.chan_shape)))
         torch.cuda.synchronize()
         ref = oracle.correlate(Z, S)
         got = vis_complex(V.cpu().numpy()).reshape(ref.shape)
@@ -208,26 +217,26 @@ def test_x_fp32_matches_oracle(S, n_c):
 
 
 def test_x_ignores_columns_beyond_n_c():
-    """Columns in [N_c, pitch) of a caller buffer do not enter the sums."""
+    """Positions in [N_c, pitch) of a caller buffer do not enter the sums."""
     S, n_c = 5, 70
     b = _binding()
+    rng = np.random.default_rng(0)
     for mode in (synth.X_FP32, synth.X_FP16_SPLIT, synth.X_INT8):
         _say(f"CASE x_pad mode={mode}")
         st = synth.CI8 if mode == synth.X_INT8 else synth.CI16
         w = _small(S=S, SB=1, n_c=n_c, st=st, mode=mode)
         with b.plan_for(w) as plan:
-            torch.manual_seed(0)
-            base = torch.zeros(plan.chan_shape, dtype=torch.float32)
-            base.uniform_(-3, 3)
-            if mode == synth.X_INT8:
-                clean = base.round().to(torch.int8)
-            else:
-                clean = base.to(plan.chan_dtype)
-            dirty = clean.clone()
-            clean[..., n_c:, :] = 0
-            dirty[..., n_c:, :] = 5
-            v1 = plan.correlate_channelized(clean.cuda())
-            v2 = plan.correlate_channelized(dirty.cuda())
+            dt = {synth.X_FP32: np.float32, synth.X_FP16_SPLIT: np.float16, synth.X_INT8: np.int8}[mode]
+            rows = [np.rint(rng.uniform(-3, 3, (64, 2 * S, plan.pitch, 2))).astype(dt) for _ in range(2)]
+            bufs = []
+            for fill in (0, 5):
+                rr = [r.copy() for r in rows]
+                for r in rr:
+                    r[..., n_c:, :] = fill
+                arr = block_planes(*rr) if mode == synth.X_FP16_SPLIT else block(rr[0])
+                bufs.append(_to_dev(arr.reshape(plan.chan_shape)))
+            v1 = plan.correlate_channelized(bufs[0])
+            v2 = plan.correlate_channelized(bufs[1])
             torch.cuda.synchronize()
             assert torch.equal(v1, v2)
 

@@ -1,0 +1,97 @@
+"""Planted mistakes in the FP64 reference are caught by its pins.
+
+Each case swaps one function of ``oracle.fx`` for a copy with a plausible mistake (dropped
+tap, reversed taps, wrong delay sign or frequency, unshifted channel order, normalised FFT,
+missing bandpass, conjugate on the wrong operand, interpolation at the wrong time point,
+rounding half away from zero) and runs the pin that must reject it.  Everything runs on the
+CPU; nothing here touches the HIP library.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.fx as fx
+from tests import test_oracle_pins as pins
+
+_orig = {name: getattr(fx, name) for name in (
+    "polyphase_filterbank", "channel_sky_freqs", "delay_cycles", "fine_delay_bandpass",
+    "correlate", "requantise_int8")}
+
+
+def _ppf_dropped_tap(timeline, h, C, T):
+    h = np.array(h, np.float64)
+    h[(T - 1) * C:] = 0.0                      # last tap row ignored
+    return _orig["polyphase_filterbank"](timeline, h, C, T)
+
+
+def _ppf_reversed_taps(timeline, h, C, T):
+    h = np.asarray(h, np.float64).reshape(T, C)[::-1].reshape(-1)
+    return _orig["polyphase_filterbank"](timeline, h, C, T)
+
+
+def _ppf_no_shift(timeline, h, C, T):
+    X = _orig["polyphase_filterbank"](timeline, h, C, T)
+    return np.roll(X, -(C // 2), axis=-1)      # DFT bin order instead of ascending frequency
+
+
+def _ppf_normalised(timeline, h, C, T):
+    return _orig["polyphase_filterbank"](timeline, h, C, T) / C
+
+
+def _freqs_without_offset(f_sb, C, f_s):
+    c = np.arange(C, dtype=np.float64)
+    return f_sb + c * (f_s / C)
+
+
+def _delay_wrong_time(f_c, tau0, tau1, n_c):
+    j = np.arange(n_c, dtype=np.float64) + 0.5
+    tau = tau0 + (tau1 - tau0) * j / n_c
+    return tau[:, None] * np.asarray(f_c, np.float64)[None, :]
+
+
+def _rotate_wrong_sign(X, cyc, bandpass):
+    return _orig["fine_delay_bandpass"](X, -np.asarray(cyc), bandpass)
+
+
+def _rotate_no_bandpass(X, cyc, bandpass):
+    return _orig["fine_delay_bandpass"](X, cyc, np.ones_like(np.asarray(bandpass, np.float64)))
+
+
+def _correlate_conj_first(Z, S, P=2):
+    Z = np.asarray(Z, np.complex128)
+    Vfull = np.matmul(np.conj(Z), np.swapaxes(Z, -1, -2))
+    return oracle.visibilities_from_full(Vfull, S, P)
+
+
+def _requant_half_away(Z, gain):
+    g = np.float64(np.float32(gain))
+    Z = np.asarray(Z, np.complex128)
+    out = np.empty(Z.shape + (2,), np.int8)
+    for comp, part in ((0, Z.real), (1, Z.imag)):
+        v = (g * part).astype(np.float32).astype(np.float64)
+        out[..., comp] = np.clip(np.sign(v) * np.floor(np.abs(v) + 0.5), -127, 127).astype(np.int8)
+    return out
+
+
+MUTANTS = [
+    ("polyphase_filterbank", _ppf_dropped_tap, pins.test_bin_centred_tone_lands_in_its_channel_with_fir_gain, ()),
+    ("polyphase_filterbank", _ppf_reversed_taps, pins.test_single_channel_is_plain_fir, ()),
+    ("polyphase_filterbank", _ppf_no_shift, pins.test_impulse_response_closed_form, (8,)),
+    ("polyphase_filterbank", _ppf_normalised, pins.test_dft_unnormalised_parseval, ()),
+    ("channel_sky_freqs", _freqs_without_offset, pins.test_delay_sign_and_frequency_align_a_delayed_sky_tone, ()),
+    ("delay_cycles", _delay_wrong_time, pins.test_linear_delay_drift_geometric_series, ()),
+    ("fine_delay_bandpass", _rotate_wrong_sign, pins.test_delay_sign_and_frequency_align_a_delayed_sky_tone, ()),
+    ("fine_delay_bandpass", _rotate_no_bandpass, pins.test_autocorrelation_closed_form, ()),
+    ("correlate", _correlate_conj_first, pins.test_correlate_matches_loops, ()),
+    ("requantise_int8", _requant_half_away, pins.test_requantise_rounding_and_clipping, ()),
+]
+
+
+@pytest.mark.parametrize("name,mutant,pin,args", MUTANTS, ids=[f"{m[0]}:{m[1].__name__}" for m in MUTANTS])
+def test_planted_mistake_is_caught(monkeypatch, name, mutant, pin, args):
+    pin(*args)                                  # the pin passes on the real reference
+    monkeypatch.setattr(fx, name, mutant)       # used inside fx_block
+    monkeypatch.setattr(oracle, name, mutant)   # used by the pins directly
+    with pytest.raises(AssertionError):
+        pin(*args)
