@@ -18,9 +18,17 @@
  *    once.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
  *    enqueues work and returns; results are ready when the stream reaches that point.
- *    Successive calls on one plan are ordered even across streams (the plan waits on its
- *    previous call's completion event).  Two host threads must not call into one plan at
- *    the same time (COBALT_EBUSY).  Different plans may run concurrently.
+ *  - Stateful calls (cobalt_correlate, cobalt_channelize, cobalt_reset_history: they use the
+ *    FIR history, the delay staging and, for cobalt_correlate, the plan's channelised
+ *    buffer) are ordered among themselves even across streams (the plan waits on its
+ *    previous stateful call's completion event); two host threads must not make stateful
+ *    calls on one plan at the same time (COBALT_EBUSY).
+ *  - Stateless calls (cobalt_correlate_channelized, cobalt_apply_gains,
+ *    cobalt_apply_gains_adjoint) read only the plan's fixed sizes: they are ordered by the
+ *    caller's stream alone, may be made from any host thread, and may overlap stateful
+ *    calls on other streams (e.g. the X stage of block k with the F stage of block k+1 into
+ *    a second channelised buffer).  The caller orders buffer reuse with its own events.
+ *  - Different plans may run concurrently.
  *  - Return value: COBALT_OK (0) or a negative COBALT_E* code; cobalt_last_error() gives a
  *    message (thread-local).  No C++ exception crosses this boundary.
  *
@@ -138,14 +146,36 @@ int cobalt_channelize(cobalt_plan* plan, const void* d_in, const double* h_delay
                       void* d_chan, void* stream);
 
 /* X stage only, on a caller-provided channelised buffer in this plan's mode and layout
- * (columns >= N_c are ignored).  Does not touch the FIR history.  Errors: EINVAL, EBUSY,
- * EDEVICE. */
+ * (positions >= N_c are ignored).  Stateless (see above).  Errors: EINVAL, EDEVICE. */
 int cobalt_correlate_channelized(cobalt_plan* plan, const void* d_chan, void* d_vis,
                                  void* stream);
 
 /* Zero the FIR history (start of a new observation / after a gap in the stream).
  * Errors: EINVAL, EBUSY, EDEVICE. */
 int cobalt_reset_history(cobalt_plan* plan, void* stream);
+
+/* Gain-applied visibilities (FP32 and FP16-split modes): complex gains per input, subband
+ * and channel, constant over the block, applied to the channelised samples before the X stage
+ * scale each stored entry:  d_vis[sb][c][bl][q] = g[a] conj(g[b]) d_vis0[sb][c][bl][q] with
+ * a = 2 s1 + p1, b = 2 s2 + p2.  d_gains: float (re, im) [SB][C][M]; d_vis0, d_vis: the
+ * visibility layout (d_vis may equal d_vis0).  Stateless.  Errors: EINVAL, EUNSUPPORTED
+ * (INT8 mode), EDEVICE.  (The differentiable correlator of the 16-bit path.) */
+int cobalt_apply_gains(cobalt_plan* plan, const void* d_vis0, const void* d_gains, void* d_vis,
+                       void* stream);
+
+/* Adjoint of cobalt_apply_gains.  Given the upstream gradient d_grad_vis = dL/dRe V + i dL/dIm V
+ * of a real loss L (visibility layout), writes d_grad_gains[sb][c][k] = dL/dRe g_k + i dL/dIm g_k:
+ *   sum over stored entries with b = k of conj(G) g[a] V0  +  with a = k of G g[b] conj(V0).
+ * Deterministic (fixed summation order, no atomics).  d_grad_gains must not alias the inputs.
+ * Errors as cobalt_apply_gains. */
+int cobalt_apply_gains_adjoint(cobalt_plan* plan, const void* d_vis0, const void* d_gains,
+                               const void* d_grad_vis, void* d_grad_gains, void* stream);
+
+/* Plain device-to-device copy of `bytes` (a multiple of 16; 16-byte aligned pointers) on the
+ * current device, 16 bytes per lane.  Reference kernel for calibrating HBM traffic counters
+ * and for an HBM readiness check before timing (the paper verifies performance with
+ * operational readiness scripts, sec. 8).  Errors: EINVAL, EDEVICE. */
+int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
 
 /* Wait for the plan's last call, then free everything it owns.  NULL is a no-op.
  * Errors: EDEVICE (the plan is freed anyway). */

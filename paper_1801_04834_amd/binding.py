@@ -24,7 +24,8 @@ _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW"
 
 EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_plan_query", "cobalt_correlate",
             "cobalt_channelize", "cobalt_correlate_channelized", "cobalt_reset_history",
-            "cobalt_plan_destroy", "cobalt_last_error"]
+            "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_plan_destroy",
+            "cobalt_last_error"]
 
 
 class CobaltError(RuntimeError):
@@ -70,6 +71,9 @@ def load_library():
     lib.cobalt_channelize.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
     lib.cobalt_correlate_channelized.argtypes = [vp, vp, vp, vp]
     lib.cobalt_reset_history.argtypes = [vp, vp]
+    lib.cobalt_apply_gains.argtypes = [vp, vp, vp, vp, vp]
+    lib.cobalt_apply_gains_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.cobalt_device_copy.argtypes = [vp, vp, ct.c_size_t, vp]
     lib.cobalt_plan_destroy.argtypes = [vp]
     lib.cobalt_last_error.argtypes = []
     lib.cobalt_last_error.restype = ct.c_char_p
@@ -117,6 +121,17 @@ def estimate_bytes(**kw) -> int:
     _check(load_library().cobalt_estimate_bytes(ct.byref(cfg), ct.byref(out)))
     del keep
     return int(out.value)
+
+
+def device_copy(dst, src, stream=None):
+    """Plain 16-byte-per-lane copy between two contiguous device tensors of equal size."""
+    import torch
+    if dst.numel() * dst.element_size() != src.numel() * src.element_size():
+        raise ValueError("size mismatch")
+    _check(load_library().cobalt_device_copy(ct.c_void_p(dst.data_ptr()), ct.c_void_p(src.data_ptr()),
+                                             dst.numel() * dst.element_size(),
+                                             _stream_handle(torch, stream, dst.device)))
+    return dst
 
 
 def _stream_handle(torch, stream, device):
@@ -238,6 +253,32 @@ class Plan:
             self._ptr, self._dev(chan, self.chan_shape, self.chan_dtype, "chan"),
             self._dev(out, self.vis_shape, self.vis_dtype, "out"),
             _stream_handle(self._torch, stream, self.device)))
+        return out
+
+    @property
+    def gains_shape(self):
+        return (self.SB, self.C, self.M)
+
+    def apply_gains(self, vis0, gains, out=None, stream=None):
+        """V'[sb,c,bl,q] = g[a] conj(g[b]) V0[sb,c,bl,q]; complex64 tensors (vis [SB,C,B,4],
+        gains [SB,C,M])."""
+        t = self._torch
+        out = t.empty_like(vis0) if out is None else out
+        vshape = self.vis_shape[:-1]
+        _check(self._lib.cobalt_apply_gains(
+            self._ptr, self._dev(vis0, vshape, t.complex64, "vis0"), self._dev(gains, self.gains_shape, t.complex64, "gains"),
+            self._dev(out, vshape, t.complex64, "out"), _stream_handle(t, stream, self.device)))
+        return out
+
+    def apply_gains_adjoint(self, vis0, gains, grad_vis, out=None, stream=None):
+        """dL/dg (dL/dRe g + i dL/dIm g) from the upstream gradient with respect to V'."""
+        t = self._torch
+        out = t.empty_like(gains) if out is None else out
+        vshape = self.vis_shape[:-1]
+        _check(self._lib.cobalt_apply_gains_adjoint(
+            self._ptr, self._dev(vis0, vshape, t.complex64, "vis0"), self._dev(gains, self.gains_shape, t.complex64, "gains"),
+            self._dev(grad_vis, vshape, t.complex64, "grad_vis"), self._dev(out, self.gains_shape, t.complex64, "out"),
+            _stream_handle(t, stream, self.device)))
         return out
 
     def reset_history(self, stream=None):

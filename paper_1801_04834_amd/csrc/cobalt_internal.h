@@ -49,5 +49,9 @@ hipError_t launch_fstage(int sample_type, int x_mode, const FArgs& a, int n_stre
 hipError_t launch_xstage_mfma(int x_mode, const XArgs& a, hipStream_t st);
 hipError_t launch_xstage_fp32(const XArgs& a, hipStream_t st);
 hipError_t launch_zero_fill(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
+hipError_t launch_apply_gains(const void* vis0, const void* gains, void* vis, int n_chan, int S, hipStream_t st);
+hipError_t launch_apply_gains_adjoint(const void* vis0, const void* gains, const void* grad_vis, void* grad_gains, int n_chan,
+                                      int S, hipStream_t st);
 
 }  // namespace cobalt

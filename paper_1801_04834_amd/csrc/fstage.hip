@@ -133,6 +133,39 @@ template <> struct Samp<ST_CF32> {
     static __device__ __forceinline__ float2 cvt(raw_t w) { return w; }
 };
 
+// One pass of input rows (32 rows x this lane's phase).  8-bit samples are packed two
+// rows per VGPR (16-bit halves), wider samples take one element per row.
+template <int ST>
+struct PassBuf {
+    using raw_t = typename Samp<ST>::raw_t;
+    raw_t v[kPass];
+    __device__ __forceinline__ void load(const raw_t* __restrict__ in, uint32_t ulane, int jb, int n_c) {
+        if (jb + kPass <= n_c) {
+#pragma unroll
+            for (int r = 0; r < kPass; ++r) v[r] = in[(uint32_t)((jb + r) * kC) + ulane];
+        } else {
+#pragma unroll
+            for (int r = 0; r < kPass; ++r) v[r] = jb + r < n_c ? in[(uint32_t)((jb + r) * kC) + ulane] : raw_t{};
+        }
+    }
+    __device__ __forceinline__ raw_t get(int r) const { return v[r]; }
+};
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+template <>
+struct PassBuf<ST_CI8> {
+    ushort2v v[kPass / 2];
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ in, uint32_t ulane, int jb, int n_c) {
+        if (jb + kPass <= n_c) {
+#pragma unroll
+            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = in[(uint32_t)((jb + r) * kC) + ulane];
+        } else {
+#pragma unroll
+            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = jb + r < n_c ? in[(uint32_t)((jb + r) * kC) + ulane] : (uint16_t)0;
+        }
+    }
+    __device__ __forceinline__ uint16_t get(int r) const { return v[r / 2][r % 2]; }
+};
+
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
 struct __attribute__((aligned(2))) char2_t { int8_t x, y; };
@@ -149,8 +182,13 @@ __device__ __forceinline__ float2 phasor_rev(double cyc) {
     return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }
 
+// Waves per SIMD each instantiation is compiled for: 3 where the registers fit without
+// spilling, 2 otherwise.
 template <int ST, int OM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fstage_kernel(FArgs a) {
+constexpr int fstage_waves() { return (ST == ST_CF32 || (ST == ST_CI16 && OM == XM_FP16_SPLIT)) ? 3 : 2; }
+
+template <int ST, int OM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves<ST, OM>()))) void fstage_kernel(FArgs a) {
     using S_ = Samp<ST>;
     using raw_t = typename S_::raw_t;
     using O_ = OutFmt<OM>;
@@ -212,15 +250,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fs
         }
     }
 
+    // Rows of the next pass are requested right after the FIR has consumed the current ones,
+    // so their HBM latency overlaps the FFT, delay and store work of this pass (8/16-bit
+    // samples; float samples, 2 VGPRs each, are loaded at the top of the pass instead).
+    constexpr bool kPrefetch = ST != ST_CF32;
+    PassBuf<ST> nw;
+    if constexpr (kPrefetch) nw.load(in, ulane, j0, a.n_c);
+
     for (int jb = j0; jb < jend; jb += kPass) {
-        raw_t nw[kPass];
-        if (jb + kPass <= a.n_c) {
-#pragma unroll
-            for (int r = 0; r < kPass; ++r) nw[r] = in[(uint32_t)((jb + r) * kC) + ulane];
-        } else {
-#pragma unroll
-            for (int r = 0; r < kPass; ++r) nw[r] = jb + r < a.n_c ? in[(uint32_t)((jb + r) * kC) + ulane] : raw_t{};
-        }
+        if constexpr (!kPrefetch) nw.load(in, ulane, jb, a.n_c);
 
         // ---- polyphase FIR: y_j[p] = sum_t h[t*C + p] x[(j - T + 1 + t)*C + p] ----
         // input-stationary: window row w feeds outputs j = w - t (taps in ascending t)
@@ -229,7 +267,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fs
         for (int j = 0; j < kPass; ++j) acc[j] = make_float2(0.f, 0.f);
 #pragma unroll
         for (int w = 0; w < kPass + kHistRows; ++w) {
-            const float2 x = S_::cvt(w < kHistRows ? tail[w] : nw[w - kHistRows]);
+            const float2 x = S_::cvt(w < kHistRows ? tail[w] : nw.get(w - kHistRows));
 #pragma unroll
             for (int t = 0; t < kT; ++t) {
                 const int j = w - t;
@@ -240,7 +278,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fs
             }
         }
 #pragma unroll
-        for (int i = 0; i < kHistRows; ++i) tail[i] = nw[kPass - kHistRows + i];
+        for (int i = 0; i < kHistRows; ++i) tail[i] = nw.get(kPass - kHistRows + i);
+        if constexpr (kPrefetch) {
+            if (jb + kPass < jend) nw.load(in, ulane, jb + kPass, a.n_c);
+        }
 
         // ---- first DIF stage across lanes p, p+32 (two channel samples per swap) ----
 #pragma unroll

@@ -391,21 +391,16 @@ int cobalt_channelize(cobalt_plan* p, const void* d_in, const double* h_delays, 
     return do_fx(p, d_in, h_delays, d_chan, nullptr, stream);
 }
 
+// Stateless with respect to the plan (reads only its immutable sizes): ordered by the
+// caller's stream alone, so it can overlap the plan's F-stage calls on another stream.
 int cobalt_correlate_channelized(cobalt_plan* p, const void* d_chan, void* d_vis, void* stream) {
     g_last_error.clear();
     if (!p) return fail(COBALT_EINVAL, "plan is NULL");
     if ((!d_chan && p->z.chan_bytes > 0) || !d_vis) return fail(COBALT_EINVAL, "d_chan or d_vis is NULL");
     if (((uintptr_t)d_chan | (uintptr_t)d_vis) % 16) return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
-    CallLock lock(p);
-    if (!lock.owns()) return fail(COBALT_EBUSY, "plan is in use by another host thread");
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
-    hipStream_t st = (hipStream_t)stream;
-    int rc = begin_call(p, st);
-    if (rc) return rc;
-    rc = run_xstage(p, d_chan, d_vis, st);
-    if (rc) return rc;
-    return end_call(p, st);
+    return run_xstage(p, d_chan, d_vis, (hipStream_t)stream);
 }
 
 int cobalt_reset_history(cobalt_plan* p, void* stream) {
@@ -421,6 +416,42 @@ int cobalt_reset_history(cobalt_plan* p, void* stream) {
     hipError_t e = launch_zero_fill(p->d_hist[p->hist_cur], round_up(p->z.hist_bytes, 256), st);
     if (e != hipSuccess) return hip_fail(e, "history reset");
     return end_call(p, st);
+}
+
+// Stateless like cobalt_correlate_channelized: ordered by the caller's stream alone.
+static int gains_call(cobalt_plan* p, const void* a0, const void* a1, const void* a2, void* out, void* stream, bool adjoint) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    if (p->cfg.x_mode == COBALT_X_INT8) return fail(COBALT_EUNSUPPORTED, "gains need float visibilities (FP32 or FP16-split mode)");
+    if (!a0 || !a1 || (adjoint && !a2) || !out) return fail(COBALT_EINVAL, "NULL device pointer");
+    if (((uintptr_t)a0 | (uintptr_t)a1 | (uintptr_t)a2 | (uintptr_t)out) % 16)
+        return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    const int n_chan = (int)(p->z.SB * kC), S = (int)p->z.S;
+    hipError_t e = adjoint ? launch_apply_gains_adjoint(a0, a1, a2, out, n_chan, S, st)
+                           : launch_apply_gains(a0, a1, out, n_chan, S, st);
+    if (e != hipSuccess) return hip_fail(e, adjoint ? "gain adjoint launch" : "gain launch");
+    return COBALT_OK;
+}
+
+int cobalt_apply_gains(cobalt_plan* p, const void* d_vis0, const void* d_gains, void* d_vis, void* stream) {
+    return gains_call(p, d_vis0, d_gains, nullptr, d_vis, stream, false);
+}
+
+int cobalt_apply_gains_adjoint(cobalt_plan* p, const void* d_vis0, const void* d_gains, const void* d_grad_vis,
+                               void* d_grad_gains, void* stream) {
+    return gains_call(p, d_vis0, d_gains, d_grad_vis, d_grad_gains, stream, true);
+}
+
+int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream) {
+    g_last_error.clear();
+    if ((!d_dst || !d_src) && bytes > 0) return fail(COBALT_EINVAL, "NULL device pointer");
+    if (((uintptr_t)d_dst | (uintptr_t)d_src | bytes) % 16) return fail(COBALT_EINVAL, "pointers and size must be multiples of 16 bytes");
+    hipError_t e = launch_device_copy(d_dst, d_src, (int64_t)bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return COBALT_OK;
 }
 
 int cobalt_plan_destroy(cobalt_plan* p) {

@@ -62,19 +62,22 @@ constexpr unsigned wave_blocks(int R, int W, bool as_b) {
 
 template <int MODE> struct XCfg;
 template <> struct XCfg<XM_FP16_SPLIT> {
-    static constexpr int kKc = 32;            // complex samples per LDS chunk
-    static constexpr int kRowB = 272;         // hi 128 B + lo 128 B + 16 B pad
+    static constexpr int kKc = 32;            // complex samples per chunk (one K block)
     static constexpr int kSteps = 4;          // k-steps of 16 halves per chunk
     using acc_t = floatx16;
     using frag_t = half8;
 };
 template <> struct XCfg<XM_INT8> {
-    static constexpr int kKc = 64;
-    static constexpr int kRowB = 144;         // 128 B + 16 B pad
-    static constexpr int kSteps = 4;          // k-steps of 32 bytes per chunk
+    static constexpr int kKc = 128;           // complex samples per chunk (four K blocks)
+    static constexpr int kSteps = 8;          // k-steps of 32 bytes per chunk
     using acc_t = intx16;
     using frag_t = intx4;
 };
+constexpr int kRowB = 256;                    // LDS bytes per row and chunk (16 granules of 16 B)
+
+// LDS rows are XOR-swizzled in 16-byte granules (granule g of row r is stored at g ^ (r%16)),
+// so the 32 rows of one MFMA fragment read hit distinct banks without padding.
+__device__ __forceinline__ int lds_off(int row, int g) { return row * kRowB + ((g ^ (row & 15)) << 4); }
 
 // (re, im) -> (-im, re) on packed fp16 pairs
 __device__ __forceinline__ uintx4 swapneg_f16(uintx4 d) {
@@ -95,71 +98,53 @@ __device__ __forceinline__ uintx4 swapneg_i8(uintx4 d) {
     return r;
 }
 
-// One K chunk of all R*32 rows, staged global -> registers -> LDS.  Each thread owns
-// kPieces 16-byte pieces; rows >= M and columns >= N_c are zero.  The loads for the next
-// chunk are issued before the MFMAs of the current one, so HBM latency hides behind them.
-template <int MODE, int R>
-struct Stage {
-    static constexpr int kPieces = MODE == XM_FP16_SPLIT ? R * 32 * 16 / 256 : R * 32 * 8 / 256;
-    uint4 v[kPieces > 0 ? kPieces : 1];
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-    __device__ __forceinline__ void load(const XArgs& a, const char* __restrict__ chan, int kc0, int tid) {
-#pragma unroll
-        for (int i = 0; i < kPieces; ++i) {
-            const int id = tid + 256 * i;
-            uint4 x = make_uint4(0, 0, 0, 0);
-            if constexpr (MODE == XM_FP16_SPLIT) {
-                const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
-                const int col0 = kc0 + seg * 4;
-                if (row < a.M) {
-                    // K block kc0/32: [hi: M rows x 128 B][lo: M rows x 128 B], contiguous
-                    const char* blk = chan + (int64_t)(kc0 / kKBlock) * (2 * a.M * 128);
-                    x = *(const uint4*)(blk + pl * (a.M * 128) + row * 128 + seg * 16);
-                    if (col0 + 4 > a.n_c) {
-                        if (col0 + 0 >= a.n_c) x.x = 0;
-                        if (col0 + 1 >= a.n_c) x.y = 0;
-                        if (col0 + 2 >= a.n_c) x.z = 0;
-                        if (col0 + 3 >= a.n_c) x.w = 0;
-                    }
-                }
-            } else {
-                const int row = id >> 3, seg = id & 7;
-                const int col0 = kc0 + seg * 8;
-                const int kb = kc0 / kKBlock + (seg >> 2);      // two K blocks of 64 B rows
-                if (row < a.M && kb < a.n_kb) {
-                    x = *(const uint4*)(chan + (int64_t)kb * (a.M * 64) + row * 64 + (seg & 3) * 16);
-                    const int keep = a.n_c - col0;             // complex samples to keep
-                    if (keep < 8) {
-                        unsigned w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int k0 = 2 * e;              // two char2 per dword
-                            if (k0 >= keep) w[e] = 0;
-                            else if (k0 + 1 >= keep) w[e] &= 0x0000ffffu;
-                        }
-                        x = make_uint4(w[0], w[1], w[2], w[3]);
-                    }
-                }
-            }
-            v[i] = x;
+// Issue the global -> LDS transfers of one chunk (rows < M) into LDS buffer `buf`.  One
+// instruction moves 64 lanes x 16 B into 1 KB of consecutive LDS (4 rows); lane L of
+// instruction i fills row 4i + L/16, stored granule L%16.  Rows >= M are never written.
+//   FP16-split chunk = K block kb: [hi: M rows x 128 B][lo: M rows x 128 B]; logical granule
+//   g < 8 is hi bytes 16g.., g >= 8 lo bytes 16(g-8)...
+//   int8 chunk = K blocks kb..kb+3, each [M rows x 64 B]; logical granule g is block g/4,
+//   bytes 16(g%4)...  Blocks past the last one are not loaded.
+template <int MODE>
+__device__ __forceinline__ void issue_chunk(const XArgs& a, const char* __restrict__ chan, char* buf, int kc0, int wave, int lane) {
+    const int n_inst = (a.M + 3) / 4;
+    const int rsub = lane >> 4, p = lane & 15;
+    for (int i = wave; i < n_inst; i += 4) {
+        const int row = 4 * i + rsub;
+        const int g = p ^ (row & 15);
+        const char* src;
+        bool ok = row < a.M;
+        if constexpr (MODE == XM_FP16_SPLIT) {
+            const char* blk = chan + (int64_t)(kc0 / kKBlock) * (2 * a.M * 128);
+            src = blk + (g >> 3) * (a.M * 128) + row * 128 + (g & 7) * 16;
+        } else {
+            const int kb = kc0 / kKBlock + (g >> 2);
+            ok = ok && kb < a.n_kb;
+            src = chan + (int64_t)kb * (a.M * 64) + row * 64 + (g & 3) * 16;
+        }
+        if (ok) __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr_t)(buf + i * 1024), 16, 0, 0);
+    }
+}
+
+// Zero the LDS entries of columns >= N_c (the last, partial chunk) and of K blocks that were
+// not loaded, for rows < M.
+template <int MODE>
+__device__ __forceinline__ void zero_tail(const XArgs& a, char* buf, int kc0, int tid) {
+    constexpr int kKc = XCfg<MODE>::kKc;
+    const int first = a.n_c - kc0;                     // first column to clear
+    const int cols = kKc - first;
+    for (int id = tid; id < a.M * cols; id += 256) {
+        const int row = id / cols, c = first + id % cols;
+        if constexpr (MODE == XM_FP16_SPLIT) {
+            *(unsigned*)(buf + lds_off(row, c >> 2) + (c & 3) * 4) = 0u;        // hi
+            *(unsigned*)(buf + lds_off(row, 8 + (c >> 2)) + (c & 3) * 4) = 0u;  // lo
+        } else {
+            *(unsigned short*)(buf + lds_off(row, c >> 3) + (c & 7) * 2) = 0;
         }
     }
-
-    __device__ __forceinline__ void store(char* lds, int tid) const {
-        using C_ = XCfg<MODE>;
-#pragma unroll
-        for (int i = 0; i < kPieces; ++i) {
-            const int id = tid + 256 * i;
-            if constexpr (MODE == XM_FP16_SPLIT) {
-                const int row = id >> 4, part = id & 15, pl = part >> 3, seg = part & 7;
-                *(uint4*)(lds + row * C_::kRowB + pl * 128 + seg * 16) = v[i];
-            } else {
-                const int row = id >> 3, seg = id & 7;
-                *(uint4*)(lds + row * C_::kRowB + seg * 16) = v[i];
-            }
-        }
-    }
-};
+}
 
 template <int MODE, int R, int W>
 __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ chan, char* lds, int tid) {
@@ -171,6 +156,7 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
     constexpr int NW = NT - T0 <= 0 ? 0 : (NT - T0 > kTilesPerWave ? kTilesPerWave : NT - T0);
     constexpr unsigned useA = wave_blocks(R, W, false) | wave_blocks(R, W, true);
     constexpr unsigned useB = wave_blocks(R, W, true);
+    constexpr int kBufB = R * 32 * kRowB;
     const int lane = tid & 63;
 
     acc_t vre[kTilesPerWave], vim[kTilesPerWave];
@@ -180,24 +166,36 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
         vim[t] = acc_t{};
     }
 
-    Stage<MODE, R> stage;
-    if (a.n_c > 0) stage.load(a, chan, 0, tid);
+    // rows M .. 32R-1 stay zero in both buffers
+    for (int off = a.M * kRowB + tid * 16; off < kBufB; off += 256 * 16) {
+        *(uint4*)(lds + off) = make_uint4(0, 0, 0, 0);
+        *(uint4*)(lds + kBufB + off) = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    if (a.n_c > 0) issue_chunk<MODE>(a, chan, lds, 0, W, lane);
+
+    int cur = 0;
     for (int kc0 = 0; kc0 < a.n_c; kc0 += C_::kKc) {
-        __syncthreads();                                   // LDS free: previous chunk consumed
-        stage.store(lds, tid);
-        __syncthreads();
-        if (kc0 + C_::kKc < a.n_c) stage.load(a, chan, kc0 + C_::kKc, tid);
+        char* buf = lds + cur * kBufB;
+        __builtin_amdgcn_s_waitcnt(0);        // this wave's transfers of chunk kc0 have landed
+        __syncthreads();                      // ... and everyone's; the other buffer is free
+        if (kc0 + C_::kKc < a.n_c) issue_chunk<MODE>(a, chan, lds + (cur ^ 1) * kBufB, kc0 + C_::kKc, W, lane);
+        if (kc0 + C_::kKc > a.n_c) {          // last, partial chunk (uniform)
+            zero_tail<MODE>(a, buf, kc0, tid);
+            __syncthreads();
+        }
         if constexpr (NW > 0) {
 #pragma unroll
             for (int ks = 0; ks < C_::kSteps; ++ks) {
-                const int off = (lane & 31) * C_::kRowB + ks * 32 + (lane >> 5) * 16;
+                const int row = lane & 31;
+                const int g = 2 * ks + (lane >> 5);
                 if constexpr (MODE == XM_FP16_SPLIT) {
                     uintx4 fh[R], fl[R], gh[R], gl[R];
                     static_for<R>([&](auto bi) {
                         constexpr int b = decltype(bi)::value;
                         if constexpr ((useA >> b) & 1u) {
-                            fh[b] = *(const uintx4*)(lds + b * 32 * C_::kRowB + off);
-                            fl[b] = *(const uintx4*)(lds + b * 32 * C_::kRowB + off + 128);
+                            fh[b] = *(const uintx4*)(buf + lds_off(32 * b + row, g));
+                            fl[b] = *(const uintx4*)(buf + lds_off(32 * b + row, 8 + g));
                         }
                         if constexpr ((useB >> b) & 1u) {
                             gh[b] = swapneg_f16(fh[b]);
@@ -207,36 +205,37 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
                     // three products, each over all tiles: independent accumulators between
                     // dependent MFMAs
                     static_for<3>([&](auto pi) {
-                        constexpr int p = decltype(pi)::value;
+                        constexpr int pr = decltype(pi)::value;
                         static_for<NW>([&](auto ti) {
                             constexpr int t = decltype(ti)::value;
                             constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
-                            const frag_t A = __builtin_bit_cast(frag_t, p == 2 ? fl[I] : fh[I]);
-                            const frag_t B = __builtin_bit_cast(frag_t, p == 1 ? fl[J] : fh[J]);
-                            const frag_t Bs = __builtin_bit_cast(frag_t, p == 1 ? gl[J] : gh[J]);
+                            const frag_t A = __builtin_bit_cast(frag_t, pr == 2 ? fl[I] : fh[I]);
+                            const frag_t B = __builtin_bit_cast(frag_t, pr == 1 ? fl[J] : fh[J]);
+                            const frag_t Bs = __builtin_bit_cast(frag_t, pr == 1 ? gl[J] : gh[J]);
                             vre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, vre[t], 0, 0, 0);
                             vim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Bs, vim[t], 0, 0, 0);
                         });
                     });
                 } else {
-                    uintx4 f[R], g[R];
+                    uintx4 f[R], gg[R];
                     static_for<R>([&](auto bi) {
                         constexpr int b = decltype(bi)::value;
-                        if constexpr ((useA >> b) & 1u) f[b] = *(const uintx4*)(lds + b * 32 * C_::kRowB + off);
-                        if constexpr ((useB >> b) & 1u) g[b] = swapneg_i8(f[b]);
+                        if constexpr ((useA >> b) & 1u) f[b] = *(const uintx4*)(buf + lds_off(32 * b + row, g));
+                        if constexpr ((useB >> b) & 1u) gg[b] = swapneg_i8(f[b]);
                     });
                     static_for<NW>([&](auto ti) {
                         constexpr int t = decltype(ti)::value;
                         constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
                         const frag_t A = __builtin_bit_cast(frag_t, f[I]);
                         const frag_t B = __builtin_bit_cast(frag_t, f[J]);
-                        const frag_t Bs = __builtin_bit_cast(frag_t, g[J]);
+                        const frag_t Bs = __builtin_bit_cast(frag_t, gg[J]);
                         vre[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B, vre[t], 0, 0, 0);
                         vim[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, Bs, vim[t], 0, 0, 0);
                     });
                 }
             }
         }
+        cur ^= 1;
     }
 
     // ---- epilogue: stored baselines s1 >= s2, all four polarisation products ----
@@ -270,8 +269,7 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
 
 template <int MODE, int R>
 __global__ __launch_bounds__(256, 2) void xstage_mfma_kernel(XArgs a) {
-    using C_ = XCfg<MODE>;
-    __shared__ __attribute__((aligned(16))) char lds[R * 32 * C_::kRowB];
+    __shared__ __attribute__((aligned(1024))) char lds[2 * R * 32 * kRowB];   // two chunk buffers
     const int tid = threadIdx.x;
     const char* chan = (const char*)a.chan + (int64_t)blockIdx.x * a.chan_stride;
     switch (tid >> 6) {

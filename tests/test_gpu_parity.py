@@ -443,3 +443,32 @@ def test_calls_on_two_streams_are_ordered():
         torch.cuda.synchronize()
         for k in range(4):
             assert torch.equal(ref[k], got[k])
+
+
+def test_pipelined_f_and_x_on_two_streams_match_serial():
+    """F of block k+1 on one stream overlapping X of block k on another (two channelised
+    buffers, events) gives the same visibilities as the serial chain."""
+    w = _small(S=6, SB=2, n_c=512, st=synth.CI16, mode=synth.X_FP16_SPLIT, seed=59)
+    _say("CASE pipelined two streams")
+    b = _binding()
+    xs = [_to_dev(w.block(k)) for k in range(5)]
+    with b.plan_for(w) as p1, b.plan_for(w) as p2:
+        ref = [p1.correlate(xs[k], w.delays(k)).clone() for k in range(5)]
+        torch.cuda.synchronize()
+        sF, sX = torch.cuda.Stream(), torch.cuda.Stream()
+        chans = [p2.empty_chan(), p2.empty_chan()]
+        outs = [p2.empty_vis() for _ in range(5)]
+        f_done = [torch.cuda.Event() for _ in range(2)]
+        x_done = [torch.cuda.Event() for _ in range(2)]
+        for k in range(5):
+            bb = k % 2
+            if k >= 2:
+                sF.wait_event(x_done[bb])
+            p2.channelize(xs[k], w.delays(k), out=chans[bb], stream=sF)
+            f_done[bb].record(sF)
+            sX.wait_event(f_done[bb])
+            p2.correlate_channelized(chans[bb], out=outs[k], stream=sX)
+            x_done[bb].record(sX)
+        torch.cuda.synchronize()
+        for k in range(5):
+            assert torch.equal(ref[k], outs[k])
