@@ -11,7 +11,9 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.flags as ofl
 import oracle.fx as fx
+from tests import test_oracle_flags as fpins
 from tests import test_oracle_pins as pins
 
 _orig = {name: getattr(fx, name) for name in (
@@ -72,6 +74,47 @@ def _requant_half_away(Z, gain):
         v = (g * part).astype(np.float32).astype(np.float64)
         out[..., comp] = np.clip(np.sign(v) * np.floor(np.abs(v) + 0.5), -127, 127).astype(np.int8)
     return out
+
+
+_orig_fl = {name: getattr(ofl, name) for name in ("channel_flags", "visibility_weights", "coarse_window")}
+
+
+def _flags_short_window(win_flags, hist_row_flags, C, T):
+    return _orig_fl["channel_flags"](win_flags, hist_row_flags, C, T - 1)
+
+
+def _flags_ignore_history(win_flags, hist_row_flags, C, T):
+    return _orig_fl["channel_flags"](win_flags, np.zeros_like(np.asarray(hist_row_flags, bool)), C, T)
+
+
+def _weights_union(chan_flags):
+    S = chan_flags.shape[0]
+    W = np.zeros((chan_flags.shape[1], S * (S + 1) // 2), np.int64)
+    for s1 in range(S):
+        for s2 in range(s1 + 1):
+            W[:, oracle.baseline_index(s1, s2)] = np.sum(~chan_flags[s1] | ~chan_flags[s2], axis=-1)
+    return W
+
+
+def _window_reversed(rows, offsets, N):
+    G = np.asarray(rows).shape[-1] - N
+    return _orig_fl["coarse_window"](rows, G - np.asarray(offsets), N)
+
+
+FLAG_MUTANTS = [
+    ("channel_flags", _flags_short_window, fpins.test_flagged_channel_samples_are_exactly_those_reading_lost_samples, (1,)),
+    ("channel_flags", _flags_ignore_history, fpins.test_flagged_channel_samples_are_exactly_those_reading_lost_samples, (2,)),
+    ("visibility_weights", _weights_union, fpins.test_weights_and_visibilities_are_sums_over_common_valid_samples, ("fp32",)),
+    ("coarse_window", _window_reversed, fpins.test_integer_sample_delay_is_removed_exactly_by_the_window_offset, ()),
+]
+
+
+@pytest.mark.parametrize("name,mutant,pin,args", FLAG_MUTANTS, ids=[f"{m[0]}:{m[1].__name__}" for m in FLAG_MUTANTS])
+def test_planted_flag_mistake_is_caught(monkeypatch, name, mutant, pin, args):
+    pin(*args)
+    monkeypatch.setattr(ofl, name, mutant)
+    with pytest.raises(AssertionError):
+        pin(*args)
 
 
 MUTANTS = [
