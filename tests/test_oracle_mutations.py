@@ -11,8 +11,10 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.beam as obm
 import oracle.flags as ofl
 import oracle.fx as fx
+from tests import test_oracle_beam as bpins
 from tests import test_oracle_flags as fpins
 from tests import test_oracle_pins as pins
 
@@ -113,6 +115,41 @@ FLAG_MUTANTS = [
 def test_planted_flag_mistake_is_caught(monkeypatch, name, mutant, pin, args):
     pin(*args)
     monkeypatch.setattr(ofl, name, mutant)
+    with pytest.raises(AssertionError):
+        pin(*args)
+
+
+_orig_bm = {name: getattr(obm, name) for name in ("beam_weights", "stokes", "incoherent_stokes")}
+
+
+def _weights_conjugated(f_c, dtau):
+    return np.conj(_orig_bm["beam_weights"](f_c, dtau))
+
+
+def _stokes_u_v_swapped(X, Y, which="IQUV"):
+    st = _orig_bm["stokes"](X, Y, "IQUV")
+    st = st[..., [0, 1, 3, 2], :]
+    return st if which == "IQUV" else st[..., :1, :]
+
+
+def _incoherent_one_pol(Z, S, P=2, which="IQUV"):
+    Z = np.asarray(Z, np.complex128)
+    Zp = Z.reshape(Z.shape[0], S, P, Z.shape[-1])
+    return _orig_bm["stokes"](Zp[:, :, 0], 0 * Zp[:, :, 1], which).sum(axis=1)
+
+
+BEAM_MUTANTS = [
+    ("beam_weights", _weights_conjugated, bpins.test_point_source_gains, ()),
+    ("stokes", _stokes_u_v_swapped, bpins.test_point_source_gains, ()),
+    ("incoherent_stokes", _incoherent_one_pol,
+     bpins.test_coherent_power_is_the_quadratic_form_of_the_correlation_matrix, ()),
+]
+
+
+@pytest.mark.parametrize("name,mutant,pin,args", BEAM_MUTANTS, ids=[f"{m[0]}:{m[1].__name__}" for m in BEAM_MUTANTS])
+def test_planted_beam_mistake_is_caught(monkeypatch, name, mutant, pin, args):
+    pin(*args)
+    monkeypatch.setattr(obm, name, mutant)
     with pytest.raises(AssertionError):
         pin(*args)
 
