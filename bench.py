@@ -44,6 +44,17 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the plain FP32 form (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subbands", type=int, default=6, help="subbands in the oracle sample")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="time only the serial F-then-X schedule (value = serial rate); for profiling runs")
+    ap.add_argument("--flags-steps", type=int, default=3,
+                    help="steps of the coarse-delay + lost-sample-flag path (0: skip)")
+    ap.add_argument("--beam-steps", type=int, default=3,
+                    help="steps of the beamformer workload (48 stations, 61 subbands, 256 channels, 127 beams; 0: skip)")
+    ap.add_argument("--service", action="store_true",
+                    help="streaming service run instead: three concurrent observations (24/48/76 stations, "
+                         "32/64/128 subbands, ci16/ci16/ci8), Poisson block arrivals, HBM-budget admission")
+    ap.add_argument("--service-seconds", type=float, default=20.0)
+    ap.add_argument("--service-budget-gib", type=float, default=48.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
@@ -113,6 +124,73 @@ def time_pipelined(torch, plan, x, delays, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def time_flagged(torch, binding, synth, plan, w, x, delays, steps):
+    """The same block through cobalt_correlate_ex: rows with a guard of 2048 samples (32
+    rows), per-station coarse offsets across the guard, lost packets of 16 samples with
+    probability 0.2 % per station and subband, and weights.  Returns per-step times (ms) of
+    the flagged call and of the plain call, each F + flags + X on one stream."""
+    G = 2048
+    xg = torch.empty((w.S, 2, w.SB, w.N + G, 2), dtype=x.dtype, device=x.device)
+    xg[:, :, :, :w.N].copy_(x)
+    xg[:, :, :, w.N:].copy_(x[:, :, :, :G])
+    offs = np.random.default_rng([w.seed, 0xC0]).integers(0, G + 1, w.S).astype(np.int32)
+    fl = synth.lost_sample_flags(w.seed, w.S, w.SB, w.N + G, p_packet=0.002, p_sample=0.0)
+    fd = torch.from_numpy(synth.pack_flags(fl).view(np.int32)).to(x.device)
+    wts = torch.empty(plan.weights_shape(), dtype=torch.int32, device=x.device)
+    vis = plan.empty_vis()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    plan.correlate_ex(xg, delays, coarse=offs, flags=fd, weights=wts, out=vis)
+    plan.correlate(x, delays, out=vis)
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record()
+        plan.correlate_ex(xg, delays, coarse=offs, flags=fd, weights=wts, out=vis)
+        ev[k][1].record()
+        plan.correlate(x, delays, out=vis)     # the next plain call still runs the flag kernel
+        ev[k][2].record()                      # for the carried rows; measured as the plain path
+    torch.cuda.synchronize()
+    flagged = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    plain = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    lost = float(fl.mean())
+    del xg, fd, vis
+    return flagged, plain, lost, float(wts.float().mean().item()) / w.n_c
+
+
+def time_beamformer(torch, binding, synth, steps, device):
+    """The beamformer workload: 48 stations x 2 pol, 61 subbands of 16-bit samples (a quarter of
+    the paper's 244-subband beamformer requirement), 256 channels, 127 coherent beams with
+    Stokes I summed over 16 channel samples, plus the incoherent Stokes I beam.  Returns
+    per-step F-stage and beamformer times (ms) and the workload's sizes."""
+    w = synth.Workload(name="beam_share", S=48, SB=61, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, C=256,
+                       sigma=64.0, seed=1807, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05,
+                       fp16_prescale_log2=5)
+    NB, n_int = 127, 16
+    x = make_input(w, torch, device)
+    plan = binding.plan_for(w)
+    dtau = torch.from_numpy(np.random.default_rng(1808).uniform(-2e-6, 2e-6, (NB, w.S))).to(device)
+    cs, _, isz = plan.beam_shapes(NB, 1, n_int)
+    coh = torch.empty(cs, dtype=torch.float32, device=device)
+    inc = torch.empty(isz, dtype=torch.float32, device=device)
+    chan = plan.empty_chan()
+    delays = w.delays(0)
+    plan.channelize(x, delays, out=chan)
+    plan.beamform_channelized(chan, dtau, 1, n_int, coherent=coh, incoherent=inc)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        plan.channelize(x, delays, out=chan)
+        ev[k][1].record()
+        plan.beamform_channelized(chan, dtau, 1, n_int, coherent=coh, incoherent=inc)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    f_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    b_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    plan.close()
+    del x, chan, coh, inc
+    return w, NB, n_int, f_ms, b_ms
+
+
 def block_latency(torch, plan, x, delays, n):
     """Submit one block, wait for it; host-side enqueue-to-completion time (ms)."""
     vis = plan.empty_vis()
@@ -151,6 +229,103 @@ def cpu_baseline(w, n_sub):
             "seconds": dt}
 
 
+def service_main(args, torch, binding, synth):
+    """Streaming service: each observation produces one ~1 s block per Poisson arrival (mean
+    inter-arrival = block duration); blocks are submitted from host (pinned) memory and
+    their visibilities copied back.  Reports latency percentiles against the block deadline,
+    drops, late blocks and the sustained real-time factor per observation."""
+    import threading
+    block_s = synth.BLOCK_SAMPLES / synth.SAMPLE_RATE_HZ
+    ws = [synth.Workload(name="O1", S=24, SB=32, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1805,
+                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5),
+          synth.Workload(name="O2", S=48, SB=64, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1806,
+                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5),
+          synth.Workload(name="O3", S=76, SB=128, sample_type=synth.CI8, x_mode=synth.X_INT8, sigma=16.0, seed=1807,
+                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05)]
+    t0 = time.perf_counter()
+    host = []
+    for w in ws:
+        blk = torch.empty((w.S, 2, w.SB, w.N, 2), dtype={1: torch.int8, 2: torch.int16}[w.sample_type], pin_memory=True)
+        for sb0 in range(0, w.SB, 16):
+            sbs = list(range(sb0, min(w.SB, sb0 + 16)))
+            blk[:, :, sb0:sb0 + len(sbs)].copy_(torch.from_numpy(w.block(0, subbands=sbs)))
+        host.append(blk)
+    log(f"bench: service inputs generated ({time.perf_counter() - t0:.1f} s)")
+    svc = binding.Service(int(args.service_budget_gib * 2**30), n_slots=3, queue_depth=4, deadline_s=block_s)
+    oids = [svc.open(**binding.plan_kwargs(w)) for w in ws]
+    outs = [[svc.vis_buffer(o) for _ in range(4)] for o in oids]
+    # warm-up: one block per observation
+    for i, w in enumerate(ws):
+        svc.wait(svc.submit(oids[i], host[i], w.delays(0), outs[i][0]))
+    warm_stats = svc.stats()
+    rng = np.random.default_rng(1805)
+    arrivals = []
+    for i in range(len(ws)):
+        t, k = rng.exponential(block_s), 0
+        while t < args.service_seconds:
+            arrivals.append((t, i, k))
+            t += rng.exponential(block_s)
+            k += 1
+    arrivals.sort()
+    pending = [[] for _ in ws]
+    lock = threading.Lock()
+    done = {"n": 0}
+
+    def waiter(i):
+        while True:
+            with lock:
+                item = pending[i].pop(0) if pending[i] else None
+            if item is None:
+                if done.get("stop"):
+                    return
+                time.sleep(0.001)
+                continue
+            if item >= 0:
+                svc.wait(item)
+                with lock:
+                    done["n"] += 1
+
+    ths = [threading.Thread(target=waiter, args=(i,)) for i in range(len(ws))]
+    for th in ths:
+        th.start()
+    start = time.perf_counter()
+    submitted = [0] * len(ws)
+    for t, i, k in arrivals:
+        dt = start + t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tk = svc.submit(oids[i], host[i], ws[i].delays(k), outs[i][k % 4])
+        submitted[i] += 1
+        with lock:
+            pending[i].append(tk if tk is not None else -1)
+    while True:
+        with lock:
+            if all(not p for p in pending):
+                break
+        time.sleep(0.01)
+    done["stop"] = True
+    for th in ths:
+        th.join()
+    wall = time.perf_counter() - start
+    st = svc.stats()
+    svc.destroy()
+    completed = st["completed"] - warm_stats["completed"]
+    out = {
+        "metric": METRIC, "mode": "service", "value": round(st["p99_latency_s"] * 1e3, 3), "unit": "ms p99 block latency",
+        "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": "three concurrent observations: 24 st x 32 SB ci16, 48 st x 64 SB ci16, 76 st x 128 SB ci8; "
+                               "Poisson arrivals, mean inter-arrival = block duration", "budget_gib": args.service_budget_gib,
+                   "seconds": args.service_seconds, "slots": 3},
+        "blocks_submitted": submitted, "blocks_completed": completed, "dropped": st["dropped"], "late": st["late"],
+        "p50_latency_ms": round(st["p50_latency_s"] * 1e3, 3), "p99_latency_ms": round(st["p99_latency_s"] * 1e3, 3),
+        "max_latency_ms": round(st["max_latency_s"] * 1e3, 3), "deadline_ms": round(block_s * 1e3, 3),
+        "sustained_real_time_factor_per_observation": round(completed * block_s / wall / len(ws), 3),
+        "hbm_admitted_gib": round(st["hbm_used_bytes"] / 2**30, 2),
+        "note": "latency includes host->device copy of the block and device->host copy of the visibilities",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -166,6 +341,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.service:
+        service_main(args, torch, binding, synth)
+        return
     w = synth.workload(args.workload)
     log(f"bench: workload {w.name} S={w.S} SB={w.SB} N={w.N} mode={w.x_mode}; generating input")
     t0 = time.perf_counter()
@@ -196,9 +374,12 @@ def main():
     log(f"bench: {args.steps} steps, wall {wall * 1e3:.3f} ms/step, F {np.mean(f_ms):.3f} ms, X {np.mean(x_ms):.3f} ms")
     serial_ms = wall * 1e3
     del vis
-    wall_p = time_pipelined(torch, plan, x, delays, args.steps, args.warmup)
-    log(f"bench: pipelined (F of block k+1 overlapping X of block k) {wall_p * 1e3:.3f} ms/step")
-    step_ms = wall_p * 1e3
+    if args.no_pipeline:
+        step_ms = serial_ms
+    else:
+        wall_p = time_pipelined(torch, plan, x, delays, args.steps, args.warmup)
+        log(f"bench: pipelined (F of block k+1 overlapping X of block k) {wall_p * 1e3:.3f} ms/step")
+        step_ms = wall_p * 1e3
     lat = block_latency(torch, plan, x, delays, max(args.steps, 20))
     log(f"bench: block latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
@@ -243,6 +424,33 @@ def main():
         del v32
         plan32.close()
 
+    flagged = None
+    if args.flags_steps > 0:
+        fl_ms, pl_ms, lost, wfrac = time_flagged(torch, binding, synth, plan, w, x, delays, args.flags_steps)
+        flagged = {"ms_per_step": round(float(np.mean(fl_ms)), 3), "plain_ms_per_step": round(float(np.mean(pl_ms)), 3),
+                   "lost_sample_fraction": round(lost, 5), "mean_weight_fraction": round(wfrac, 4),
+                   "guard_samples": 2048}
+        log(f"bench: coarse delay + flags {np.mean(fl_ms):.3f} ms/step vs plain {np.mean(pl_ms):.3f} ms "
+            f"(lost {lost:.4%}, mean weight {wfrac:.4f} of N_c)")
+
+    beam = None
+    if args.beam_steps > 0:
+        bw, NB, n_int, bf_ms, bb_ms = time_beamformer(torch, binding, synth, args.beam_steps, dev)
+        cmac_b = bw.SB * bw.C * NB * bw.S * 2 * bw.n_c          # useful complex MACs per block
+        b_ms = float(np.mean(bb_ms))
+        mfma_tf = cmac_b * 8 * 3 * (128 / NB) / (b_ms * 1e-3) / 1e12     # executed: 3 products, beams padded to 128
+        beam = {"workload": f"{bw.S} stations x 2 pol, {bw.SB} subbands ci16, 256 channels, {NB} beams, "
+                            f"Stokes I summed over {n_int} samples + incoherent I",
+                "f_stage_ms": round(float(np.mean(bf_ms)), 3), "beamformer_ms": round(b_ms, 3),
+                "ms_per_step": round(float(np.mean(bf_ms)) + b_ms, 3),
+                "beam_tcmacs": round(cmac_b / (b_ms * 1e-3) / 1e12, 3),
+                "real_time_factor": round(bw.N / synth.SAMPLE_RATE_HZ / ((float(np.mean(bf_ms)) + b_ms) * 1e-3), 2),
+                "roofline": {"bound": "mfma", "achieved": round(mfma_tf, 1), "peak": FP16_MFMA_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                             "kernel": "beam_kernel"}}
+        log(f"bench: beamformer F {np.mean(bf_ms):.3f} ms + beams {b_ms:.3f} ms "
+            f"({beam['beam_tcmacs']} TeraMAC/s useful, {mfma_tf:.0f} TFLOP/s executed)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"bench: oracle on {args.cpu_subbands} subband(s) for the CPU baseline")
@@ -262,7 +470,8 @@ def main():
                                f"16-tap PPF -> 64 ch, N={w.N} ({w.n_c} channel samples, {block_s:.8f} s)",
                    "stations": w.S, "subbands": w.SB, "channels": w.C, "samples_per_block": w.N,
                    "x_mode": w.x_mode},
-        "schedule": "pipelined: F stage of block k+1 overlaps X stage of block k on a second stream",
+        "schedule": ("serial: F then X on one stream" if args.no_pipeline else
+                     "pipelined: F stage of block k+1 overlaps X stage of block k on a second stream"),
         "ms_per_step_serial": round(serial_ms, 4),
         "real_time_factor": round(block_s / (step_ms * 1e-3), 2),
         "block_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
@@ -273,6 +482,8 @@ def main():
         "roofline": dominant,
         "roofline_other": other,
         "plain_fp32_form": fp32,
+        "coarse_delay_and_flags": flagged,
+        "beamformer": beam,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -18,13 +18,14 @@
  *    once.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
  *    enqueues work and returns; results are ready when the stream reaches that point.
- *  - Stateful calls (cobalt_correlate, cobalt_channelize, cobalt_reset_history: they use the
+ *  - Stateful calls (cobalt_correlate(_ex), cobalt_channelize(_ex), cobalt_beamform,
+ *    cobalt_reset_history: they use the
  *    FIR history, the delay staging and, for cobalt_correlate, the plan's channelised
  *    buffer) are ordered among themselves even across streams (the plan waits on its
  *    previous stateful call's completion event); two host threads must not make stateful
  *    calls on one plan at the same time (COBALT_EBUSY).
- *  - Stateless calls (cobalt_correlate_channelized, cobalt_apply_gains,
- *    cobalt_apply_gains_adjoint) read only the plan's fixed sizes: they are ordered by the
+ *  - Stateless calls (cobalt_correlate_channelized, cobalt_beamform_channelized,
+ *    cobalt_apply_gains, cobalt_apply_gains_adjoint) read only the plan's fixed sizes: they are ordered by the
  *    caller's stream alone, may be made from any host thread, and may overlap stateful
  *    calls on other streams (e.g. the X stage of block k with the F stage of block k+1 into
  *    a second channelised buffer).  The caller orders buffer reuse with its own events.
@@ -69,7 +70,7 @@ extern "C" {
 /* ---- return codes ------------------------------------------------------------------ */
 #define COBALT_OK            0
 #define COBALT_EINVAL       -1   /* bad argument: sizes, NULL pointers, N % C != 0 ...   */
-#define COBALT_EUNSUPPORTED -2   /* valid but not built: C != 64, T != 16, P != 2, M > 160 in MFMA modes */
+#define COBALT_EUNSUPPORTED -2   /* valid but not built: C not 64/256, T != 16, P != 2, M > 160 in MFMA modes */
 #define COBALT_EOVERFLOW    -3   /* INT8 mode with N_c * 2 * 127^2 >= 2^31 (int32 sums)   */
 #define COBALT_ENOMEM       -4   /* device or pinned host allocation failed              */
 #define COBALT_EBUSY        -5   /* another host thread is inside a call on this plan    */
@@ -91,7 +92,7 @@ typedef struct cobalt_config {
     int32_t n_stations;          /* S >= 1                                                */
     int32_t n_pols;              /* P, must be 2                                          */
     int32_t n_subbands;          /* SB >= 1                                               */
-    int32_t n_channels;          /* C, 64 (the only channel count built)                  */
+    int32_t n_channels;          /* C: 64 or 256 (the two channel counts built)           */
     int32_t n_taps;              /* T, 16 (the only tap count built)                      */
     int32_t sample_type;         /* COBALT_CI8 | COBALT_CI16 | COBALT_CF32                */
     int32_t x_mode;              /* COBALT_X_FP32 | COBALT_X_FP16_SPLIT | COBALT_X_INT8   */
@@ -145,6 +146,80 @@ int cobalt_correlate(cobalt_plan* plan, const void* d_in, const double* h_delays
 int cobalt_channelize(cobalt_plan* plan, const void* d_in, const double* h_delays,
                       void* d_chan, void* stream);
 
+/* ---- coarse delay and lost samples ---------------------------------------------------
+ * Optional per-block extras of cobalt_correlate_ex / cobalt_channelize_ex.  The paper
+ * compensates the whole-sample part of each station's delay by shifting its sample stream
+ * (sec. 7.1) and applies only the residual as the fine delay (sec. 7.5); lost input is
+ * recorded as metadata of the data product (sec. 3.2, sec. 7.2).  Here:
+ *  - Coarse delay: input rows hold row_samples = N + G samples; station s reads its block
+ *    window row[g_s .. g_s + N) (g_s = h_coarse_offset[s], 0 <= g_s <= G, shared by both
+ *    polarisations and all subbands).  The FIR history carries the end of the previous
+ *    window, so changing g_s between blocks repeats or skips samples at the block edge.
+ *    h_delays then holds the residual delays.
+ *  - Lost samples: d_flags [S][SB][flag_words] uint32, flag_words = ceil(row_samples / 32):
+ *    bit k of word w set = sample 32w + k of the row of station s, subband sb is lost (both
+ *    polarisations).  A channel sample j is flagged when any sample of its FIR window (the
+ *    T*C samples (j-T+1)*C .. (j+1)*C - 1 of the block window, reaching into the previous
+ *    block) is lost; flagged channel samples are written as zero to the channelised data, so
+ *    they drop out of every visibility.  The plan carries the flags of the last T-1 rows of C
+ *    samples to the next block (cleared by cobalt_reset_history; honoured by the plain calls
+ *    too).
+ *  - Weights: d_weights [SB][B] int32 receives, per baseline, the number of channel samples
+ *    valid for both stations (N_c when nothing is lost).
+ * Every field may be zero / NULL: row_samples 0 means N, NULL offsets mean 0, NULL flags
+ * mean nothing lost, NULL weights are not written. */
+typedef struct cobalt_block_ext {
+    int64_t         row_samples;       /* samples per input row, >= N; 0 = N                  */
+    const int32_t*  h_coarse_offset;   /* host [S], copied before return; NULL = all 0         */
+    const uint32_t* d_flags;           /* device [S][SB][flag_words], 4-byte aligned; NULL     */
+    int32_t*        d_weights;         /* device [SB][B], 4-byte aligned; NULL                 */
+} cobalt_block_ext;
+
+/* cobalt_correlate with coarse delay, lost-sample flags and weights.  d_in: [S][P][SB]
+ * [row_samples] complex samples.  ext == NULL is cobalt_correlate.  Errors: EINVAL (an
+ * offset outside 0..row_samples-N, misaligned pointers), EBUSY, EDEVICE. */
+int cobalt_correlate_ex(cobalt_plan* plan, const void* d_in, const double* h_delays,
+                        const cobalt_block_ext* ext, void* d_vis, void* stream);
+
+/* cobalt_channelize with the same extras (flagged channel samples are zero in d_chan). */
+int cobalt_channelize_ex(cobalt_plan* plan, const void* d_in, const double* h_delays,
+                         const cobalt_block_ext* ext, void* d_chan, void* stream);
+
+/* ---- beamformer ----------------------------------------------------------------------
+ * The paper's second pipeline (sec. 7.5, sec. 5): the same front end (a plan with
+ * n_channels = 256 is the paper's setting; 64 also works), then per channel
+ *   coherent beams   beam[b][p][t] = sum_s w[b][s] Z[s*P + p][t],
+ *                    w[b][s] = exp(+2 pi i f_c dtau[b][s])  (phase in FP64, reduced, FP32
+ *                    rotation), dtau = extra arrival delay of beam b's direction at station s,
+ *   Stokes           I = |X|^2 + |Y|^2, Q = |X|^2 - |Y|^2, U = 2 Re(X conj Y),
+ *                    V = 2 Im(X conj Y)  from the polarisations X (p = 0), Y (p = 1),
+ *   incoherent       per-station Stokes summed over stations,
+ * with Stokes summed over n_int consecutive channel samples.  Requires an FP16-split plan
+ * (the products run on matrix cores with hi/lo operands) and at most 56 stations.
+ * Output layouts (float, time fastest):
+ *   d_coherent    [SB][C][NB][n_stokes][N_c / n_int]
+ *   d_voltages    [SB][C][NB][P][N_c] complex (re, im)
+ *   d_incoherent  [SB][C][n_stokes][N_c / n_int]
+ * Any output may be NULL (not computed); at least one must be given. */
+typedef struct cobalt_beam_params {
+    int32_t       n_beams;      /* NB >= 1                                                  */
+    int32_t       n_stokes;     /* 1 (I) or 4 (I, Q, U, V)                                  */
+    int32_t       n_int;        /* a power of two <= 32 or a multiple of 32; divides N_c    */
+    int32_t       reserved0;    /* must be 0                                                */
+    const double* d_beam_dtau;  /* device [NB][S] seconds, 8-byte aligned                    */
+} cobalt_beam_params;
+
+/* F stage (stateful, like cobalt_correlate: advances the FIR history) into the plan's
+ * channelised buffer, then the beamformer.  Errors: EINVAL, EUNSUPPORTED (mode, stations),
+ * EBUSY, EDEVICE. */
+int cobalt_beamform(cobalt_plan* plan, const void* d_in, const double* h_delays, const cobalt_beam_params* beams,
+                    void* d_coherent, void* d_voltages, void* d_incoherent, void* stream);
+
+/* Beamformer only, on a caller-provided channelised buffer (FP16-split layout of this plan).
+ * Stateless.  Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
+int cobalt_beamform_channelized(cobalt_plan* plan, const void* d_chan, const cobalt_beam_params* beams,
+                                void* d_coherent, void* d_voltages, void* d_incoherent, void* stream);
+
 /* X stage only, on a caller-provided channelised buffer in this plan's mode and layout
  * (positions >= N_c are ignored).  Stateless (see above).  Errors: EINVAL, EDEVICE. */
 int cobalt_correlate_channelized(cobalt_plan* plan, const void* d_chan, void* d_vis,
@@ -176,6 +251,59 @@ int cobalt_apply_gains_adjoint(cobalt_plan* plan, const void* d_vis0, const void
  * and for an HBM readiness check before timing (the paper verifies performance with
  * operational readiness scripts, sec. 8).  Errors: EINVAL, EDEVICE. */
 int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
+
+/* ---- streaming service --------------------------------------------------------------
+ * ~1 s blocks from several concurrent observations.  Observations are admitted against an
+ * HBM budget; blocks wait in a bounded FIFO per observation and run on the first free stream
+ * slot, so blocks of different observations overlap on the device.  Blocks of one observation
+ * run in arrival order (the FIR history carries over).  A full FIFO drops the new block
+ * (COBALT_EBUSY) instead of stalling the producer, as the paper's pipeline drops data rather
+ * than wait (sec. 7.2).  Latency = submit -> the block's visibilities are back in host memory. */
+typedef struct cobalt_service cobalt_service;
+
+typedef struct cobalt_service_stats {
+    int64_t submitted, completed, dropped, late;   /* late: latency > deadline             */
+    double  p50_latency_s, p99_latency_s, max_latency_s;
+    int64_t hbm_used_bytes, hbm_budget_bytes;
+} cobalt_service_stats;
+
+/* Service on the current device with `n_slots` streams (1..64), per-observation FIFOs of
+ * `queue_depth` blocks and a latency deadline (s).  Starts one dispatcher thread.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int cobalt_service_create(size_t hbm_budget_bytes, int n_slots, int queue_depth, double deadline_s,
+                          cobalt_service** out);
+
+/* Admit an observation: its plan workspace plus one device input block and one visibility
+ * buffer must fit in the remaining budget, else COBALT_ENOMEM and nothing is allocated.
+ * *obs_id identifies it in later calls.  Errors: EINVAL, EUNSUPPORTED, EOVERFLOW (as
+ * cobalt_plan_create), ENOMEM, EDEVICE. */
+int cobalt_service_open(cobalt_service* svc, const cobalt_config* cfg, int* obs_id);
+
+/* Queue one block: h_block host input ([S][P][SB][N] samples; pinned memory lets the copy run
+ * asynchronously), h_delays [S][2] (copied), h_vis host output (visibility layout).  Both host
+ * buffers must stay valid until cobalt_service_wait returns for *ticket.  A full FIFO drops the
+ * block: COBALT_EBUSY with *ticket = -1.  Errors: EINVAL, EBUSY. */
+int cobalt_service_submit(cobalt_service* svc, int obs_id, const void* h_block, const double* h_delays,
+                          void* h_vis, int64_t* ticket);
+
+/* Block until `ticket` has completed; *latency_s (may be NULL) = submit -> completion.  Each
+ * ticket can be waited once.  Errors: EINVAL, EDEVICE (an asynchronous device error). */
+int cobalt_service_wait(cobalt_service* svc, int64_t ticket, double* latency_s);
+
+/* Stop (1) or resume (0) dispatching; queued blocks stay queued (tests force full FIFOs). */
+int cobalt_service_pause(cobalt_service* svc, int paused);
+
+/* Counters and latency percentiles over all completed blocks. */
+int cobalt_service_get_stats(cobalt_service* svc, cobalt_service_stats* out);
+
+/* Finish the observation's queued blocks, then free its plan and buffers (budget returns). */
+int cobalt_service_close(cobalt_service* svc, int obs_id);
+
+/* Finish all queued blocks, stop the dispatcher and free everything.  NULL is a no-op. */
+int cobalt_service_destroy(cobalt_service* svc);
+
+/* Message for the last service error on this host thread. */
+const char* cobalt_service_last_error(void);
 
 /* Wait for the plan's last call, then free everything it owns.  NULL is a no-op.
  * Errors: EDEVICE (the plan is freed anyway). */

@@ -23,9 +23,12 @@ _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW"
           EBUSY: "EBUSY", EDEVICE: "EDEVICE"}
 
 EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_plan_query", "cobalt_correlate",
-            "cobalt_channelize", "cobalt_correlate_channelized", "cobalt_reset_history",
+            "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
+            "cobalt_beamform_channelized", "cobalt_correlate_channelized", "cobalt_reset_history",
             "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_plan_destroy",
-            "cobalt_last_error"]
+            "cobalt_last_error", "cobalt_service_create", "cobalt_service_open", "cobalt_service_submit",
+            "cobalt_service_wait", "cobalt_service_pause", "cobalt_service_get_stats", "cobalt_service_close",
+            "cobalt_service_destroy", "cobalt_service_last_error"]
 
 
 class CobaltError(RuntimeError):
@@ -52,6 +55,24 @@ class PlanInfo(ct.Structure):
         "vis_bytes", "workspace_bytes", "useful_cmacs")]
 
 
+class BlockExt(ct.Structure):
+    """``cobalt_block_ext``: coarse delay offsets, lost-sample flags and weights of a block."""
+    _fields_ = [("row_samples", ct.c_int64), ("h_coarse_offset", ct.POINTER(ct.c_int32)),
+                ("d_flags", ct.c_void_p), ("d_weights", ct.c_void_p)]
+
+
+class BeamParams(ct.Structure):
+    """``cobalt_beam_params``."""
+    _fields_ = [("n_beams", ct.c_int32), ("n_stokes", ct.c_int32), ("n_int", ct.c_int32),
+                ("reserved0", ct.c_int32), ("d_beam_dtau", ct.c_void_p)]
+
+
+class ServiceStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("dropped", ct.c_int64),
+                ("late", ct.c_int64), ("p50_latency_s", ct.c_double), ("p99_latency_s", ct.c_double),
+                ("max_latency_s", ct.c_double), ("hbm_used_bytes", ct.c_int64), ("hbm_budget_bytes", ct.c_int64)]
+
+
 _LIB = None
 
 
@@ -69,6 +90,10 @@ def load_library():
     lib.cobalt_plan_query.argtypes = [vp, ct.POINTER(PlanInfo)]
     lib.cobalt_correlate.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
     lib.cobalt_channelize.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
+    lib.cobalt_correlate_ex.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BlockExt), vp, vp]
+    lib.cobalt_channelize_ex.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BlockExt), vp, vp]
+    lib.cobalt_beamform.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BeamParams), vp, vp, vp, vp]
+    lib.cobalt_beamform_channelized.argtypes = [vp, vp, ct.POINTER(BeamParams), vp, vp, vp, vp]
     lib.cobalt_correlate_channelized.argtypes = [vp, vp, vp, vp]
     lib.cobalt_reset_history.argtypes = [vp, vp]
     lib.cobalt_apply_gains.argtypes = [vp, vp, vp, vp, vp]
@@ -77,8 +102,19 @@ def load_library():
     lib.cobalt_plan_destroy.argtypes = [vp]
     lib.cobalt_last_error.argtypes = []
     lib.cobalt_last_error.restype = ct.c_char_p
-    for name in EXPORTED[:-1]:
-        getattr(lib, name).restype = i32
+    lib.cobalt_service_create.argtypes = [ct.c_size_t, i32, i32, ct.c_double, ct.POINTER(vp)]
+    lib.cobalt_service_open.argtypes = [vp, ct.POINTER(Config), ct.POINTER(i32)]
+    lib.cobalt_service_submit.argtypes = [vp, i32, vp, ct.POINTER(ct.c_double), vp, ct.POINTER(ct.c_int64)]
+    lib.cobalt_service_wait.argtypes = [vp, ct.c_int64, ct.POINTER(ct.c_double)]
+    lib.cobalt_service_pause.argtypes = [vp, i32]
+    lib.cobalt_service_get_stats.argtypes = [vp, ct.POINTER(ServiceStats)]
+    lib.cobalt_service_close.argtypes = [vp, i32]
+    lib.cobalt_service_destroy.argtypes = [vp]
+    lib.cobalt_service_last_error.argtypes = []
+    lib.cobalt_service_last_error.restype = ct.c_char_p
+    for name in EXPORTED:
+        if name not in ("cobalt_last_error", "cobalt_service_last_error"):
+            getattr(lib, name).restype = i32
     _LIB = lib
     return lib
 
@@ -246,6 +282,94 @@ class Plan:
             _stream_handle(self._torch, stream, self.device)))
         return out
 
+    def flag_words(self, row_samples=None):
+        return ((self.N if row_samples is None else row_samples) + 31) // 32
+
+    def weights_shape(self):
+        return (self.SB, self.B)
+
+    def _ext(self, x, coarse, flags, weights):
+        """Marshal the per-block extras; returns (BlockExt, keep-alive tuple, input shape)."""
+        t = self._torch
+        row = x.shape[3] if x.dim() == 5 else self.N
+        ext = BlockExt()
+        ext.row_samples = row
+        keep = []
+        if coarse is not None:
+            c = np.ascontiguousarray(coarse, np.int32).reshape(-1)
+            if c.size != self.S:
+                raise ValueError(f"coarse: need {self.S} int32 offsets")
+            ext.h_coarse_offset = c.ctypes.data_as(ct.POINTER(ct.c_int32))
+            keep.append(c)
+        if flags is not None:
+            ext.d_flags = self._dev(flags, (self.S, self.SB, self.flag_words(row)), t.int32, "flags")
+        if weights is not None:
+            ext.d_weights = self._dev(weights, self.weights_shape(), t.int32, "weights")
+        return ext, keep, (self.S, 2, self.SB, row, 2)
+
+    def correlate_ex(self, x, delays, coarse=None, flags=None, weights=None, out=None, stream=None):
+        """Full FX chain with coarse delay offsets (int32 [S], host), lost-sample flags
+        (int32 bit words [S][SB][ceil(row/32)], device) and weights (int32 [SB][B], device,
+        written).  x: [S][2][SB][row_samples][2] with row_samples >= N."""
+        out = self.empty_vis() if out is None else out
+        d = self._delays(delays)
+        ext, keep, shape = self._ext(x, coarse, flags, weights)
+        _check(self._lib.cobalt_correlate_ex(
+            self._ptr, self._dev(x, shape, self.input_dtype, "x"), d.ctypes.data_as(ct.POINTER(ct.c_double)),
+            ct.byref(ext), self._dev(out, self.vis_shape, self.vis_dtype, "out"),
+            _stream_handle(self._torch, stream, self.device)))
+        del keep
+        return out
+
+    def channelize_ex(self, x, delays, coarse=None, flags=None, weights=None, out=None, stream=None):
+        """F stage with the same extras as ``correlate_ex``; returns the channelised tensor."""
+        out = self.empty_chan() if out is None else out
+        d = self._delays(delays)
+        ext, keep, shape = self._ext(x, coarse, flags, weights)
+        _check(self._lib.cobalt_channelize_ex(
+            self._ptr, self._dev(x, shape, self.input_dtype, "x"), d.ctypes.data_as(ct.POINTER(ct.c_double)),
+            ct.byref(ext), self._dev(out, self.chan_shape, self.chan_dtype, "out"),
+            _stream_handle(self._torch, stream, self.device)))
+        del keep
+        return out
+
+    # ---- beamformer --------------------------------------------------------------------
+    def beam_shapes(self, n_beams, n_stokes=4, n_int=1):
+        """Shapes of the coherent Stokes, voltage and incoherent Stokes outputs."""
+        n_out = self.n_c // n_int
+        return ((self.SB, self.C, n_beams, n_stokes, n_out), (self.SB, self.C, n_beams, 2, self.n_c, 2),
+                (self.SB, self.C, n_stokes, n_out))
+
+    def _beam_call(self, fn, first, delays, dtau, n_stokes, n_int, coherent, voltages, incoherent, stream):
+        t = self._torch
+        if dtau.dtype != t.float64 or dtau.dim() != 2 or dtau.shape[1] != self.S:
+            raise ValueError(f"dtau: need float64 [NB][{self.S}] on the device")
+        nb = dtau.shape[0]
+        cs, vs, isz = self.beam_shapes(nb, n_stokes, n_int)
+        bp = BeamParams(nb, n_stokes, n_int, 0, self._dev(dtau, tuple(dtau.shape), t.float64, "dtau"))
+        ptr = lambda x, shp, dt, name: None if x is None else self._dev(x, shp, dt, name)  # noqa: E731
+        args = [self._ptr, first]
+        if delays is not None:
+            d = self._delays(delays)
+            args.append(d.ctypes.data_as(ct.POINTER(ct.c_double)))
+        args += [ct.byref(bp), ptr(coherent, cs, t.float32, "coherent"), ptr(voltages, vs, t.float32, "voltages"),
+                 ptr(incoherent, isz, t.float32, "incoherent"), _stream_handle(t, stream, self.device)]
+        _check(fn(*args))
+        return coherent, voltages, incoherent
+
+    def beamform(self, x, delays, dtau, n_stokes=4, n_int=1, coherent=None, voltages=None, incoherent=None,
+                 stream=None):
+        """F stage + beamformer; outputs are caller tensors (float32, ``beam_shapes``)."""
+        return self._beam_call(self._lib.cobalt_beamform, self._dev(x, self.input_shape, self.input_dtype, "x"),
+                               delays, dtau, n_stokes, n_int, coherent, voltages, incoherent, stream)
+
+    def beamform_channelized(self, chan, dtau, n_stokes=4, n_int=1, coherent=None, voltages=None, incoherent=None,
+                             stream=None):
+        """Beamformer only on a channelised tensor of this plan."""
+        return self._beam_call(self._lib.cobalt_beamform_channelized,
+                               self._dev(chan, self.chan_shape, self.chan_dtype, "chan"), None, dtau, n_stokes, n_int,
+                               coherent, voltages, incoherent, stream)
+
     def correlate_channelized(self, chan, out=None, stream=None):
         """X stage only on a channelised tensor; returns the visibility tensor."""
         out = self.empty_vis() if out is None else out
@@ -308,6 +432,125 @@ def plan_for(workload, **overrides):
     kw = dict(n_stations=workload.S, n_subbands=workload.SB, samples_per_block=workload.N,
               sample_type=workload.sample_type, x_mode=workload.x_mode, fir=workload.fir(),
               subband_freqs=workload.subband_freqs(), bandpass=workload.bandpass(),
-              requant_gain=workload.gain(), fp16_prescale_log2=workload.fp16_prescale_log2)
+              requant_gain=workload.gain(), fp16_prescale_log2=workload.fp16_prescale_log2,
+              n_channels=workload.C)
     kw.update(overrides)
     return Plan(**kw)
+
+
+def _scheck(rc):
+    if rc != COBALT_OK:
+        msg = load_library().cobalt_service_last_error().decode(errors="replace")
+        raise CobaltError(rc, msg)
+
+
+def _host_ptr(a):
+    """Data pointer of a contiguous host numpy array or CPU torch tensor."""
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("host buffer must be contiguous")
+        return ct.c_void_p(a.ctypes.data)
+    if a.is_cuda or not a.is_contiguous():
+        raise ValueError("host buffer must be a contiguous CPU tensor")
+    return ct.c_void_p(a.data_ptr())
+
+
+class Service:
+    """Streaming service (``cobalt_service``): observations admitted by HBM budget, blocks
+    dispatched to free stream slots as they arrive.  Host buffers passed to ``submit`` are
+    kept referenced until ``wait`` returns for their ticket (use pinned tensors for
+    asynchronous copies)."""
+
+    def __init__(self, hbm_budget_bytes, n_slots=4, queue_depth=4, deadline_s=196608 / 195312.5):
+        import torch
+        self._lib = load_library()
+        self._ptr = ct.c_void_p(None)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        _scheck(self._lib.cobalt_service_create(int(hbm_budget_bytes), int(n_slots), int(queue_depth),
+                                                float(deadline_s), ct.byref(self._ptr)))
+        self._obs = {}
+        self._held = {}
+
+    def open(self, **kw):
+        """Admit an observation (keywords as ``Plan``); returns its id.  Raises CobaltError
+        with code ENOMEM when the HBM budget cannot hold it."""
+        cfg, keep = make_config(**kw)
+        oid = ct.c_int(-1)
+        _scheck(self._lib.cobalt_service_open(self._ptr, ct.byref(cfg), ct.byref(oid)))
+        S, SB = kw["n_stations"], kw["n_subbands"]
+        B = S * (S + 1) // 2
+        vis_dtype = np.int32 if kw["x_mode"] == X_INT8 else np.float32
+        self._obs[oid.value] = dict(kw=kw, keep=keep, S=S, vis_shape=(SB, kw.get("n_channels", 64), B, 4, 2),
+                                    vis_dtype=vis_dtype)
+        return oid.value
+
+    def vis_buffer(self, obs_id, pinned=True):
+        """A host buffer for one block's visibilities of this observation."""
+        import torch
+        o = self._obs[obs_id]
+        dt = torch.int32 if o["vis_dtype"] == np.int32 else torch.float32
+        return torch.empty(o["vis_shape"], dtype=dt, pin_memory=pinned)
+
+    def submit(self, obs_id, h_block, delays, h_vis):
+        """Queue one block; returns its ticket, or None when the FIFO was full (dropped)."""
+        d = np.ascontiguousarray(delays, np.float64).reshape(-1)
+        if d.size != 2 * self._obs[obs_id]["S"]:
+            raise ValueError("delays: need S x 2 float64 seconds")
+        t = ct.c_int64(-1)
+        rc = self._lib.cobalt_service_submit(self._ptr, int(obs_id), _host_ptr(h_block),
+                                             d.ctypes.data_as(ct.POINTER(ct.c_double)), _host_ptr(h_vis), ct.byref(t))
+        if rc == EBUSY:
+            return None
+        _scheck(rc)
+        self._held[t.value] = (h_block, h_vis)
+        return t.value
+
+    def wait(self, ticket):
+        """Block until the ticket completes; returns its latency in seconds."""
+        lat = ct.c_double(0)
+        rc = self._lib.cobalt_service_wait(self._ptr, ct.c_int64(ticket), ct.byref(lat))
+        self._held.pop(ticket, None)
+        _scheck(rc)
+        return lat.value
+
+    def pause(self, paused=True):
+        _scheck(self._lib.cobalt_service_pause(self._ptr, 1 if paused else 0))
+
+    def stats(self):
+        st = ServiceStats()
+        _scheck(self._lib.cobalt_service_get_stats(self._ptr, ct.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServiceStats._fields_}
+
+    def close(self, obs_id):
+        _scheck(self._lib.cobalt_service_close(self._ptr, int(obs_id)))
+        self._obs.pop(obs_id, None)
+
+    def destroy(self):
+        if self._ptr is not None and self._ptr.value:
+            rc = self._lib.cobalt_service_destroy(self._ptr)
+            self._ptr = ct.c_void_p(None)
+            self._held.clear()
+            _scheck(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def plan_kwargs(workload, **overrides):
+    """Plan keyword arguments of a ``synth.Workload``."""
+    kw = dict(n_stations=workload.S, n_subbands=workload.SB, samples_per_block=workload.N,
+              sample_type=workload.sample_type, x_mode=workload.x_mode, fir=workload.fir(),
+              subband_freqs=workload.subband_freqs(), bandpass=workload.bandpass(),
+              requant_gain=workload.gain(), fp16_prescale_log2=workload.fp16_prescale_log2,
+              n_channels=workload.C)
+    kw.update(overrides)
+    return kw

@@ -7,12 +7,11 @@
 
 namespace cobalt {
 
-// Built instantiation: C = 64 channels, T = 16 taps (the paper's 64-channel correlator
-// setting with a 16-tap polyphase FIR).
-constexpr int kC = 64;
+// Built instantiations: C = 64 channels (the correlator setting) and C = 256 (the paper's
+// beamformer front end and the correlator's finest resolution), T = 16 taps.
+constexpr int kC = 64;                         // channels of the flag path (one row = two flag words)
 constexpr int kT = 16;
 constexpr int kHistRows = kT - 1;              // FIR history in rows of C samples
-constexpr int kHist = kHistRows * kC;          // 960 samples carried per input stream
 constexpr int kKBlock = 32;                    // channel samples per K block of the channelised layout
 constexpr int kPitchAlign = kKBlock;           // channelised rows padded to whole K blocks
 constexpr int kMaxMfmaInputs = 160;            // 5 row blocks of 32 (80 stations)
@@ -23,17 +22,33 @@ enum SampleType { ST_CI8 = 1, ST_CI16 = 2, ST_CF32 = 3 };
 enum XMode { XM_FP32 = 0, XM_FP16_SPLIT = 1, XM_INT8 = 2 };
 
 struct FArgs {
-    const void* in;          // [S][P][SB][N] samples
-    const void* hist_old;    // [S*P*SB][kHist] samples, stream order (s*P + p)*SB + sb
+    const void* in;          // [S][P][SB][row_len] samples; the block window starts at coarse[s]
+    const void* hist_old;    // [S*P*SB][kHistRows*C] samples, stream order (s*P + p)*SB + sb
     void* hist_new;          // same layout, written by the last chunk of each stream
     void* out;               // channelised buffer, K-blocked (see cobalt.h)
     const float* fir;        // [kT * kC]
     const float* bscale;     // [kC] bandpass * mode scale (2^k or requant gain)
     const double* f_sb;      // [SB] subband sky centre frequency (Hz)
     const double* delays;    // [S][2] residual delay (s) at block start / end
-    int64_t N;               // samples per block per stream
-    int32_t S, SB, M, n_c, pitch, n_chunks, n_kb;
+    const int32_t* coarse;   // [S] window start of each station in its rows, or null (0)
+    const uint32_t* cflag;   // [S*SB][n_words] flagged channel samples (bit j%32 of word j/32), or null
+    int64_t N;               // samples per block window per stream
+    int64_t row_len;         // samples per input row (N + guard)
+    int32_t C;               // channels: 64 or 256
+    int32_t S, SB, M, n_c, pitch, n_chunks, n_kb, n_words;
     double df;               // channel width f_s / C (Hz)
+};
+
+// Lost-sample flags -> flagged channel samples (FIR window rule) and the row flags carried
+// to the next block.
+struct FlagArgs {
+    const uint32_t* flags;   // [S][SB][flag_words] lost-sample bits of the input rows, or null
+    int64_t flag_words;
+    const int32_t* coarse;   // [S] or null
+    const uint32_t* hist_old;// [S*SB] flags of the kHistRows rows before the block, bits 17..31
+    uint32_t* hist_new;      // same, for the next block
+    uint32_t* cflag;         // [S*SB][n_words]
+    int32_t S, SB, n_c, n_words;
 };
 
 struct XArgs {
@@ -44,10 +59,27 @@ struct XArgs {
     float out_scale;         // FP16-split: 2^-2k
 };
 
+// Beamformer over an FP16-split channelised buffer.
+struct BeamArgs {
+    const void* chan;        // channelised buffer (FP16-split planes, K-blocked)
+    int64_t chan_stride;     // bytes per channel
+    const double* f_sb;      // [SB] subband sky centre frequency (Hz)
+    const double* dtau;      // [NB][S] beam delay offsets (s), device
+    void* coherent;          // [SB*C][NB][n_stokes][N_c/n_int] float, or null
+    void* voltages;          // [SB*C][NB][P][N_c] float (re, im), or null
+    void* incoherent;        // [SB*C][n_stokes][N_c/n_int] float, or null
+    double df;               // channel width (Hz)
+    int32_t C, S, NB, n_c, n_kb, n_chan, n_int, n_stokes;
+    float vscale;            // 2^-k: undoes the FP16-split prescale
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fstage(int sample_type, int x_mode, const FArgs& a, int n_streams, hipStream_t st);
 hipError_t launch_xstage_mfma(int x_mode, const XArgs& a, hipStream_t st);
 hipError_t launch_xstage_fp32(const XArgs& a, hipStream_t st);
+hipError_t launch_chanflags(const FlagArgs& a, hipStream_t st);
+hipError_t launch_weights(const uint32_t* cflag, int32_t* weights, int S, int SB, int n_c, int n_words, hipStream_t st);
+hipError_t launch_beamformer(const BeamArgs& a, hipStream_t st);
 hipError_t launch_zero_fill(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_apply_gains(const void* vis0, const void* gains, void* vis, int n_chan, int S, hipStream_t st);

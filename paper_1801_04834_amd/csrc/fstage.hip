@@ -135,32 +135,32 @@ template <> struct Samp<ST_CF32> {
 
 // One pass of input rows (32 rows x this lane's phase).  8-bit samples are packed two
 // rows per VGPR (16-bit halves), wider samples take one element per row.
-template <int ST>
+template <int ST, int C>
 struct PassBuf {
     using raw_t = typename Samp<ST>::raw_t;
     raw_t v[kPass];
     __device__ __forceinline__ void load(const raw_t* __restrict__ in, uint32_t ulane, int jb, int n_c) {
         if (jb + kPass <= n_c) {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r] = in[(uint32_t)((jb + r) * kC) + ulane];
+            for (int r = 0; r < kPass; ++r) v[r] = in[(uint32_t)((jb + r) * C) + ulane];
         } else {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r] = jb + r < n_c ? in[(uint32_t)((jb + r) * kC) + ulane] : raw_t{};
+            for (int r = 0; r < kPass; ++r) v[r] = jb + r < n_c ? in[(uint32_t)((jb + r) * C) + ulane] : raw_t{};
         }
     }
     __device__ __forceinline__ raw_t get(int r) const { return v[r]; }
 };
 typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
-template <>
-struct PassBuf<ST_CI8> {
+template <int C>
+struct PassBuf<ST_CI8, C> {
     ushort2v v[kPass / 2];
     __device__ __forceinline__ void load(const uint16_t* __restrict__ in, uint32_t ulane, int jb, int n_c) {
         if (jb + kPass <= n_c) {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = in[(uint32_t)((jb + r) * kC) + ulane];
+            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = in[(uint32_t)((jb + r) * C) + ulane];
         } else {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = jb + r < n_c ? in[(uint32_t)((jb + r) * kC) + ulane] : (uint16_t)0;
+            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = jb + r < n_c ? in[(uint32_t)((jb + r) * C) + ulane] : (uint16_t)0;
         }
     }
     __device__ __forceinline__ uint16_t get(int r) const { return v[r / 2][r % 2]; }
@@ -183,18 +183,38 @@ __device__ __forceinline__ float2 phasor_rev(double cyc) {
 }
 
 // Waves per SIMD each instantiation is compiled for: 3 where the registers fit without
-// spilling, 2 otherwise.
-template <int ST, int OM>
-constexpr int fstage_waves() { return (ST == ST_CF32 || (ST == ST_CI16 && OM == XM_FP16_SPLIT)) ? 3 : 2; }
+// spilling (64 channels), 2 otherwise; 256 channels are limited to 2 by LDS anyway.
+template <int ST, int OM, int C>
+constexpr int fstage_waves() { return C == 64 && (ST == ST_CF32 || (ST == ST_CI16 && OM == XM_FP16_SPLIT)) ? 3 : 2; }
 
-template <int ST, int OM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves<ST, OM>()))) void fstage_kernel(FArgs a) {
+// C = 64: one wave per workgroup; lane p is FIR phase p and the 64-point FFT is the
+// lane-pair stage + LDS + 32-point DFT per lane described above.
+// C = 256: four waves per workgroup; wave m holds FIR phases 64m + p.  A radix-4
+// decimation-in-frequency stage across the waves (through LDS) leaves wave r with
+//   z_r[p] = exp(-2 pi i r p / 256) sum_m y[p + 64m] (-i)^(m r),
+// whose 64-point DFT is bins k = 4k' + r of the 256-point DFT; that 64-point DFT then runs
+// exactly as for C = 64.
+template <int ST, int OM, int C>
+__global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<ST, OM, C>()))) void fstage_kernel(FArgs a) {
+    static_assert(C == 64 || C == 256, "64 or 256 channels");
+    constexpr int kW = C / 64;                 // waves per workgroup
+    constexpr int kHistC = kHistRows * C;      // history samples per stream
     using S_ = Samp<ST>;
     using raw_t = typename S_::raw_t;
     using O_ = OutFmt<OM>;
-    __shared__ float2 ylds[kPass * kRowF2];
+    // per-wave FFT staging rows; for C = 256 the same memory first holds the radix-4
+    // exchange (all waves' FIR outputs of the pass)
+    constexpr int kYl = kPass * kRowF2;
+    constexpr int kXch = kW > 1 ? kW * kPass * 64 : 0;
+    __shared__ float2 lds_f2[kW * kYl > kXch ? kW * kYl : kXch];
+    // Bandpass x mode scale per channel, staged in LDS: reading it from global memory in the
+    // store loop would put a vector-memory wait on every channel, and such a wait also waits
+    // for the prefetched rows of the next pass.  (The first pass's barrier orders this write.)
+    __shared__ float blds[C];
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = kW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;   // wave index
+    float2* const ylds = lds_f2 + wv * kYl;
     // grid order: input row fastest, so neighbouring rows of one channel K block are
     // written by concurrently running waves (contiguous in the K-blocked layout)
     const int row_in = (int)(blockIdx.x % (unsigned)a.M);               // input index s*P + p
@@ -204,11 +224,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
     const int64_t st = (int64_t)row_in * a.SB + sb;                      // input stream (s*P + p)*SB + sb
     const int s = row_in >> 1;
     // wave-uniform bases; per-lane offsets below stay within 2^31 bytes
-    const raw_t* __restrict__ in = (const raw_t*)a.in + st * a.N;
-    const raw_t* __restrict__ hold = (const raw_t*)a.hist_old + st * kHist;
+    // block window of this stream: its row, shifted by the station's coarse delay
+    const raw_t* __restrict__ in = (const raw_t*)a.in + st * a.row_len + (a.coarse ? a.coarse[s] : 0);
+    // flagged channel samples of this station and subband (one bit per channel sample)
+    const uint32_t* __restrict__ cflag = a.cflag ? a.cflag + ((int64_t)s * a.SB + sb) * a.n_words : nullptr;
+    const raw_t* __restrict__ hold = (const raw_t*)a.hist_old + st * kHistC;
+    // this wave's FIR phases 64 wv .. 64 wv + 63
+    const raw_t* __restrict__ inw = in + 64 * wv;
+    const raw_t* __restrict__ holdw = hold + 64 * wv;
     // channelised layout [SB][C][n_kb][planes][M][32]: element (row, j) of channel c lives
     // in K block j/32 at position j%32 of the row
-    char* __restrict__ out = (char*)a.out + ((int64_t)sb * kC * a.n_kb * O_::kPlanes * a.M + row_in) * kKBlock * O_::kElem;
+    char* __restrict__ out = (char*)a.out + ((int64_t)sb * C * a.n_kb * O_::kPlanes * a.M + row_in) * kKBlock * O_::kElem;
     const uint32_t cstride = (uint32_t)(a.n_kb * O_::kPlanes * a.M * kKBlock * O_::kElem);   // bytes between channels
     const uint32_t pstride = (uint32_t)(a.M * kKBlock * O_::kElem);                          // bytes between planes
     const uint32_t kbstride = (uint32_t)(O_::kPlanes * a.M * kKBlock * O_::kElem);           // bytes between K blocks
@@ -217,16 +243,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
     // The last chunk of every stream writes the history for the next block: the final
     // (T-1)*C samples of [old history, block].
     if (chunk == a.n_chunks - 1) {
-        raw_t* hnew = (raw_t*)a.hist_new + st * kHist;
-        for (int i = lane; i < kHist; i += 64) {
+        raw_t* hnew = (raw_t*)a.hist_new + st * kHistC;
+        for (int i = threadIdx.x; i < kHistC; i += C) {
             const int64_t t = a.N + i;
-            hnew[i] = t < kHist ? hold[t] : in[t - kHist];
+            hnew[i] = t < kHistC ? hold[t] : in[t - kHistC];
         }
     }
 
+    for (int i = threadIdx.x; i < C; i += 64 * kW) blds[i] = a.bscale[i];
     float h[kT];
 #pragma unroll
-    for (int t = 0; t < kT; ++t) h[t] = a.fir[t * kC + lane];
+    for (int t = 0; t < kT; ++t) h[t] = a.fir[t * C + 64 * wv + lane];
+    float rtw_c = 1.f, rtw_s = 0.f;            // radix-4 twiddle exp(-2 pi i wv lane / C) = (c, -s)
+    if constexpr (kW > 1) sincospif(2.0f * (float)(wv * lane) / (float)C, &rtw_s, &rtw_c);
 
     float wsn, wcs;                            // exp(-2 pi i q / 64), q = lane mod 32
     sincospif((float)(lane & 31) / 32.0f, &wsn, &wcs);
@@ -241,12 +270,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
     raw_t tail[kHistRows];                     // raw samples of the 15 rows before the pass
     if (j0 >= kHistRows && j0 <= a.n_c) {
 #pragma unroll
-        for (int i = 0; i < kHistRows; ++i) tail[i] = in[(uint32_t)((j0 - kHistRows + i) * kC) + ulane];
+        for (int i = 0; i < kHistRows; ++i) tail[i] = inw[(uint32_t)((j0 - kHistRows + i) * C) + ulane];
     } else {
 #pragma unroll
         for (int i = 0; i < kHistRows; ++i) {
             const int r = j0 - kHistRows + i;  // wave-uniform
-            tail[i] = r < 0 ? hold[(r + kHistRows) * kC + lane] : r < a.n_c ? in[r * kC + lane] : raw_t{};
+            tail[i] = r < 0 ? holdw[(r + kHistRows) * C + lane] : r < a.n_c ? inw[r * C + lane] : raw_t{};
         }
     }
 
@@ -254,11 +283,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
     // so their HBM latency overlaps the FFT, delay and store work of this pass (8/16-bit
     // samples; float samples, 2 VGPRs each, are loaded at the top of the pass instead).
     constexpr bool kPrefetch = ST != ST_CF32;
-    PassBuf<ST> nw;
-    if constexpr (kPrefetch) nw.load(in, ulane, j0, a.n_c);
+    PassBuf<ST, C> nw;
+    if constexpr (kPrefetch) nw.load(inw, ulane, j0, a.n_c);
 
     for (int jb = j0; jb < jend; jb += kPass) {
-        if constexpr (!kPrefetch) nw.load(in, ulane, jb, a.n_c);
+        if constexpr (!kPrefetch) nw.load(inw, ulane, jb, a.n_c);
 
         // ---- polyphase FIR: y_j[p] = sum_t h[t*C + p] x[(j - T + 1 + t)*C + p] ----
         // input-stationary: window row w feeds outputs j = w - t (taps in ascending t)
@@ -280,7 +309,48 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
 #pragma unroll
         for (int i = 0; i < kHistRows; ++i) tail[i] = nw.get(kPass - kHistRows + i);
         if constexpr (kPrefetch) {
-            if (jb + kPass < jend) nw.load(in, ulane, jb + kPass, a.n_c);
+            if (jb + kPass < jend) nw.load(inw, ulane, jb + kPass, a.n_c);
+        }
+
+        // Channel samples past N_c and flagged ones (their FIR window reads a lost sample) are
+        // written as zero: their FIR outputs are cleared here, so the FFT, rotation and
+        // stores below carry zeros.  The mask is wave-uniform (bit jj = channel sample jb+jj).
+        {
+            uint32_t kill = cflag ? cflag[jb / kKBlock] : 0u;
+            if (jb + kPass > a.n_c) kill |= ~((1u << (a.n_c - jb)) - 1u);   // 1 <= n_c - jb < 32 here
+            if (kill) {
+#pragma unroll
+                for (int j = 0; j < kPass; ++j)
+                    if ((kill >> j) & 1u) acc[j] = make_float2(0.f, 0.f);
+            }
+        }
+
+        // ---- C = 256: radix-4 stage across the four waves (bins k = 4k' + wv remain) ----
+        if constexpr (kW > 1) {
+            float2* xch = lds_f2;                                     // [wave m][j][lane]
+#pragma unroll
+            for (int j = 0; j < kPass; ++j) xch[(wv * kPass + j) * 64 + lane] = acc[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kPass; ++j) {
+                const float2 a0 = xch[(0 * kPass + j) * 64 + lane], a1 = xch[(1 * kPass + j) * 64 + lane];
+                const float2 a2 = xch[(2 * kPass + j) * 64 + lane], a3 = xch[(3 * kPass + j) * 64 + lane];
+                float zr, zi;
+                if (wv == 0) {
+                    zr = (a0.x + a2.x) + (a1.x + a3.x);
+                    zi = (a0.y + a2.y) + (a1.y + a3.y);
+                } else if (wv == 2) {
+                    zr = (a0.x + a2.x) - (a1.x + a3.x);
+                    zi = (a0.y + a2.y) - (a1.y + a3.y);
+                } else {
+                    // (a0 - a2) -+ i (a1 - a3) for wv = 1 / 3
+                    const float ur = a0.x - a2.x, ui = a0.y - a2.y, vr = a1.x - a3.x, vi = a1.y - a3.y;
+                    zr = wv == 1 ? ur + vi : ur - vi;
+                    zi = wv == 1 ? ui - vr : ui + vr;
+                }
+                acc[j] = make_float2(zr * rtw_c + zi * rtw_s, zi * rtw_c - zr * rtw_s);
+            }
+            __syncthreads();                                          // the exchange is read before ylds reuse
         }
 
         // ---- first DIF stage across lanes p, p+32 (two channel samples per swap) ----
@@ -316,17 +386,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
         // cycles is f_c tau(j) = tau(j) (f_SB + (c - C/2) df), linear in q.  Exact phasors
         // (FP64 argument and reduction) every 4 steps of q, complex recurrence in between.
         const int j = jb + jj;
-        const bool live = j < a.n_c;
         const double tau = tau0 + (tau1 - tau0) * (double)j / (double)a.n_c;
         const double c1 = tau * a.df;                                  // cycles per channel
-        const double c0 = fma((double)(hh - kC / 2), c1, tau * fsb);   // cycles at q = 0
-        const float2 step = phasor_rev(2.0 * c1);                      // q -> q + 1
+        // this lane's channels: c = 2 kW q + kW hh + wv (q = 0..31)
+        const double c0 = fma((double)(kW * hh + wv - C / 2), c1, tau * fsb);   // cycles at q = 0
+        const float2 step = phasor_rev(2.0 * kW * c1);                          // q -> q + 1
         float2 ph = make_float2(1.f, 0.f);
-        const uint32_t lane_off = (uint32_t)hh * cstride + (uint32_t)(jb / kKBlock) * kbstride + (uint32_t)(jj * O_::kElem);
+        const uint32_t lane_off = (uint32_t)(kW * hh + wv) * cstride + (uint32_t)(jb / kKBlock) * kbstride + (uint32_t)(jj * O_::kElem);
+        const uint32_t lane_off_lo = lane_off + pstride;                // FP16-split lo plane
 #pragma unroll
         for (int q = 0; q < 32; ++q) {
             if (q % 4 == 0) {
-                ph = phasor_rev(fma((double)(2 * q), c1, c0));
+                ph = phasor_rev(fma((double)(2 * kW * q), c1, c0));
             } else {
                 const float pr_ = ph.x * step.x - ph.y * step.y;
                 ph.y = ph.x * step.y + ph.y * step.x;
@@ -334,22 +405,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fstage_waves
             }
             const int m = (q + 16) & 31;               // FFT bin 2m + hh is channel 2q + hh
             const int i = bitrev5(m);                  // register holding bin m
-            const float b = hh ? a.bscale[2 * q + 1] : a.bscale[2 * q];
+            const float b = blds[2 * kW * q + kW * hh + wv];   // bandpass x mode scale of channel c
             const float pr_ = ph.x * b, pi_ = ph.y * b;
-            float zr = xr[i] * pr_ - xi[i] * pi_;
-            float zi = xr[i] * pi_ + xi[i] * pr_;
-            if (!live) { zr = 0.f; zi = 0.f; }
-            const uint32_t o = lane_off + (uint32_t)(2 * q) * cstride;
-            char* dst = out + o;
+            const float zr = xr[i] * pr_ - xi[i] * pi_;
+            const float zi = xr[i] * pi_ + xi[i] * pr_;
+            // the channel's base is wave-uniform (scalar adds); lane offsets are loop-invariant
+            char* outq = out + (size_t)((uint32_t)(2 * kW * q) * cstride);
+            char* dst = outq + lane_off;
             if constexpr (OM == XM_FP32) {
                 *(float2*)dst = make_float2(zr, zi);
             } else if constexpr (OM == XM_FP16_SPLIT) {
-                // hi = fp16(z) (round to nearest even), lo = fp16(z - hi)
+                // hi = fp16(z) (round to nearest even), lo = fp16(z - hi).  z - hi is exact in
+                // FP32, so v_fma_mix{lo,hi}_f16 (z + 1 * (-hi) with hi read as fp16, result
+                // rounded once to fp16) gives the same bits as converting hi back, subtracting
+                // and converting, in one instruction per component.
                 const float2v z2 = {zr, zi};
                 const half2v hi = __builtin_convertvector(z2, half2v);
-                const half2v lo = __builtin_convertvector(z2 - __builtin_convertvector(hi, float2v), half2v);
+                const unsigned hb = __builtin_bit_cast(unsigned, hi);
+                unsigned lb;
+                asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lb) : "v"(zr), "v"(hb));
+                asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(lb) : "v"(zi), "v"(hb));
                 *(half2v*)dst = hi;
-                *(half2v*)(out + (o + pstride)) = lo;
+                *(unsigned*)(outq + lane_off_lo) = lb;
             } else {
                 const float qr = fminf(fmaxf(rintf(zr), -127.f), 127.f);
                 const float qi = fminf(fmaxf(rintf(zi), -127.f), 127.f);
@@ -370,16 +447,25 @@ __global__ void zero_fill_kernel(uint4* p, int64_t n16, uint8_t* tail, int64_t n
         for (int64_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
 }
 
-template <int ST>
+template <int ST, int C>
 hipError_t launch_st(int x_mode, const FArgs& a, int n_streams, hipStream_t st) {
-    const dim3 grid((unsigned)((int64_t)n_streams * a.n_chunks)), block(64);   // = SB * n_chunks * M
+    const dim3 grid((unsigned)((int64_t)n_streams * a.n_chunks)), block(C);   // = SB * n_chunks * M
     switch (x_mode) {
-        case XM_FP32: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP32>), grid, block, 0, st, a); break;
-        case XM_FP16_SPLIT: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP16_SPLIT>), grid, block, 0, st, a); break;
-        case XM_INT8: hipLaunchKernelGGL((fstage_kernel<ST, XM_INT8>), grid, block, 0, st, a); break;
+        case XM_FP32: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP32, C>), grid, block, 0, st, a); break;
+        case XM_FP16_SPLIT: hipLaunchKernelGGL((fstage_kernel<ST, XM_FP16_SPLIT, C>), grid, block, 0, st, a); break;
+        case XM_INT8: hipLaunchKernelGGL((fstage_kernel<ST, XM_INT8, C>), grid, block, 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int ST>
+hipError_t launch_c(int x_mode, const FArgs& a, int n_streams, hipStream_t st) {
+    switch (a.C) {
+        case 64: return launch_st<ST, 64>(x_mode, a, n_streams, st);
+        case 256: return launch_st<ST, 256>(x_mode, a, n_streams, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -387,9 +473,9 @@ hipError_t launch_st(int x_mode, const FArgs& a, int n_streams, hipStream_t st) 
 hipError_t launch_fstage(int sample_type, int x_mode, const FArgs& a, int n_streams, hipStream_t st) {
     if (n_streams <= 0 || a.n_chunks <= 0) return hipSuccess;
     switch (sample_type) {
-        case ST_CI8: return launch_st<ST_CI8>(x_mode, a, n_streams, st);
-        case ST_CI16: return launch_st<ST_CI16>(x_mode, a, n_streams, st);
-        case ST_CF32: return launch_st<ST_CF32>(x_mode, a, n_streams, st);
+        case ST_CI8: return launch_c<ST_CI8>(x_mode, a, n_streams, st);
+        case ST_CI16: return launch_c<ST_CI16>(x_mode, a, n_streams, st);
+        case ST_CF32: return launch_c<ST_CF32>(x_mode, a, n_streams, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -41,6 +41,7 @@ struct Sizes {
     int64_t S, P, SB, C, T, N, n_c, pitch, M, B, streams;
     int64_t sample_bytes, input_bytes, chan_elem_bytes, chan_planes, chan_stride, chan_bytes, vis_bytes;
     int64_t hist_bytes, table_bytes, workspace_bytes;
+    int64_t n_words, cflag_bytes, rowhist_bytes, stage_bytes;
 };
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -51,7 +52,8 @@ int validate(const cobalt_config* c, Sizes* z) {
     if (c->n_pols != 2) return fail(c->n_pols < 1 ? COBALT_EINVAL : COBALT_EUNSUPPORTED, "n_pols must be 2 (got %d)", c->n_pols);
     if (c->n_subbands < 1) return fail(COBALT_EINVAL, "n_subbands must be >= 1 (got %d)", c->n_subbands);
     if (c->n_channels < 1 || c->n_taps < 1) return fail(COBALT_EINVAL, "n_channels and n_taps must be >= 1");
-    if (c->n_channels != kC) return fail(COBALT_EUNSUPPORTED, "only %d channels are built (got %d)", kC, c->n_channels);
+    if (c->n_channels != 64 && c->n_channels != 256)
+        return fail(COBALT_EUNSUPPORTED, "only 64 and 256 channels are built (got %d)", c->n_channels);
     if (c->n_taps != kT) return fail(COBALT_EUNSUPPORTED, "only %d taps are built (got %d)", kT, c->n_taps);
     if (c->sample_type != COBALT_CI8 && c->sample_type != COBALT_CI16 && c->sample_type != COBALT_CF32)
         return fail(COBALT_EINVAL, "unknown sample_type %d", c->sample_type);
@@ -65,17 +67,17 @@ int validate(const cobalt_config* c, Sizes* z) {
     if (c->reserved0 != 0) return fail(COBALT_EINVAL, "reserved0 must be 0");
     if (!c->h_fir) return fail(COBALT_EINVAL, "h_fir is NULL");
     if (!c->h_subband_freq_hz) return fail(COBALT_EINVAL, "h_subband_freq_hz is NULL");
-    for (int i = 0; i < kT * kC; ++i)
+    for (int i = 0; i < kT * c->n_channels; ++i)
         if (!std::isfinite(c->h_fir[i])) return fail(COBALT_EINVAL, "h_fir[%d] is not finite", i);
     if (c->h_bandpass)
-        for (int i = 0; i < kC; ++i)
+        for (int i = 0; i < c->n_channels; ++i)
             if (!std::isfinite(c->h_bandpass[i])) return fail(COBALT_EINVAL, "h_bandpass[%d] is not finite", i);
     for (int i = 0; i < c->n_subbands; ++i)
         if (!std::isfinite(c->h_subband_freq_hz[i])) return fail(COBALT_EINVAL, "h_subband_freq_hz[%d] is not finite", i);
 
     Sizes s{};
-    s.S = c->n_stations; s.P = c->n_pols; s.SB = c->n_subbands; s.C = kC; s.T = kT;
-    s.N = c->samples_per_block; s.n_c = s.N / kC; s.M = s.S * s.P; s.B = s.S * (s.S + 1) / 2;
+    s.S = c->n_stations; s.P = c->n_pols; s.SB = c->n_subbands; s.C = c->n_channels; s.T = kT;
+    s.N = c->samples_per_block; s.n_c = s.N / s.C; s.M = s.S * s.P; s.B = s.S * (s.S + 1) / 2;
     s.pitch = round_up(s.n_c, kPitchAlign);
     s.streams = s.M * s.SB;
     if (s.n_c > (int64_t)1 << 30) return fail(COBALT_EINVAL, "samples_per_block too large");
@@ -102,19 +104,24 @@ int validate(const cobalt_config* c, Sizes* z) {
         // byte offsets
         const int64_t elem = c->x_mode == COBALT_X_INT8 ? 2 : c->x_mode == COBALT_X_FP16_SPLIT ? 4 : 8;
         const int64_t planes = c->x_mode == COBALT_X_FP16_SPLIT ? 2 : 1;
-        if (s.N * s.sample_bytes >= ((int64_t)1 << 31) || (int64_t)kC * planes * s.M * s.pitch * elem >= ((int64_t)1 << 31))
+        if (s.N * s.sample_bytes >= ((int64_t)1 << 31) || s.C * planes * s.M * s.pitch * elem >= ((int64_t)1 << 31))
             return fail(COBALT_EUNSUPPORTED, "block too long: one subband's channelised data must stay below 2 GiB");
     }
     s.input_bytes = s.streams * s.N * s.sample_bytes;
     s.chan_elem_bytes = c->x_mode == COBALT_X_INT8 ? 2 : c->x_mode == COBALT_X_FP16_SPLIT ? 4 : 8;
     s.chan_planes = c->x_mode == COBALT_X_FP16_SPLIT ? 2 : 1;
     s.chan_stride = s.chan_planes * s.M * s.pitch * s.chan_elem_bytes;
-    s.chan_bytes = s.SB * kC * s.chan_stride;
-    s.vis_bytes = s.SB * kC * s.B * 4 * 8;
-    s.hist_bytes = s.streams * kHist * s.sample_bytes;
-    s.table_bytes = round_up((int64_t)kT * kC * 4, 256) + round_up(kC * 4, 256) + round_up(s.SB * 8, 256) +
-                    kRing * round_up(s.S * 16, 256);
-    s.workspace_bytes = round_up(s.chan_bytes, 256) + 2 * round_up(s.hist_bytes, 256) + s.table_bytes;
+    s.chan_bytes = s.SB * s.C * s.chan_stride;
+    s.vis_bytes = s.SB * s.C * s.B * 4 * 8;
+    s.hist_bytes = s.streams * kHistRows * s.C * s.sample_bytes;
+    s.stage_bytes = round_up(s.S * 16 + s.S * 4, 256);         // per ring slot: delays [S][2], offsets [S]
+    s.table_bytes = round_up(kT * s.C * 4, 256) + round_up(s.C * 4, 256) + round_up(s.SB * 8, 256) +
+                    kRing * s.stage_bytes;
+    s.n_words = s.pitch / 32;
+    s.cflag_bytes = s.S * s.SB * s.n_words * 4;
+    s.rowhist_bytes = s.S * s.SB * 4;
+    s.workspace_bytes = round_up(s.chan_bytes, 256) + 2 * round_up(s.hist_bytes, 256) + 2 * round_up(s.rowhist_bytes, 256) +
+                        round_up(s.cflag_bytes, 256) + s.table_bytes;
     *z = s;
     return COBALT_OK;
 }
@@ -129,11 +136,15 @@ struct cobalt_plan {
     void* d_chan = nullptr;
     void* d_hist[2] = {nullptr, nullptr};
     int hist_cur = 0;
+    uint32_t* d_rowhist[2] = {nullptr, nullptr};   // lost-sample flags of the rows before the block
+    int rowhist_cur = 0;
+    bool flag_dirty = false;     // the carried row flags may be nonzero
+    uint32_t* d_cflag = nullptr; // flagged channel samples of the current block
     float* d_fir = nullptr;
     float* d_bscale = nullptr;
     double* d_fsb = nullptr;
-    double* d_delay[kRing] = {};
-    double* h_delay = nullptr;   // pinned [kRing][S][2]
+    char* d_stage[kRing] = {};   // per slot: delays [S][2] float64, coarse offsets [S] int32
+    char* h_stage = nullptr;     // pinned [kRing][stage_bytes]
     hipEvent_t ring_ev[kRing] = {};
     bool ring_used[kRing] = {};
     int ring_next = 0;
@@ -167,7 +178,7 @@ void free_plan(cobalt_plan* p) {
     for (int i = 0; i < kRing; ++i)
         if (p->ring_ev[i]) (void)hipEventDestroy(p->ring_ev[i]);
     if (p->done_ev) (void)hipEventDestroy(p->done_ev);
-    if (p->h_delay) (void)hipHostFree(p->h_delay);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->d_ws) (void)hipFree(p->d_ws);
     delete p;
 }
@@ -190,28 +201,69 @@ int end_call(cobalt_plan* p, hipStream_t st) {
 }
 
 // Copy the caller's delays into a ring slot (pinned host -> device) on stream st.
-int stage_delays(cobalt_plan* p, const double* h_delays, hipStream_t st, const double** d_out) {
+// Per-call host arrays (residual delays, coarse offsets) go through a pinned ring of kRing
+// slots, each guarded by the event of its last copy, so the caller may reuse its arrays at
+// once and the copy stays ordered on the call's stream.
+int stage_block(cobalt_plan* p, const double* h_delays, const int32_t* h_coarse, int64_t max_offset, hipStream_t st,
+                const double** d_delays, const int32_t** d_coarse) {
     const int S = (int)p->z.S;
     for (int i = 0; i < 2 * S; ++i)
         if (!std::isfinite(h_delays[i])) return fail(COBALT_EINVAL, "h_delays[%d] is not finite", i);
+    if (h_coarse)
+        for (int i = 0; i < S; ++i)
+            if (h_coarse[i] < 0 || h_coarse[i] > max_offset)
+                return fail(COBALT_EINVAL, "coarse offset of station %d is %d; must lie in 0..%lld", i, h_coarse[i],
+                            (long long)max_offset);
     const int slot = p->ring_next;
     p->ring_next = (p->ring_next + 1) % kRing;
     if (p->ring_used[slot]) {
         hipError_t e = hipEventSynchronize(p->ring_ev[slot]);   // the slot's previous copy has run
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     }
-    double* h = p->h_delay + (size_t)slot * 2 * S;
+    char* h = p->h_stage + (size_t)slot * p->z.stage_bytes;
     std::memcpy(h, h_delays, sizeof(double) * 2 * S);
-    hipError_t e = hipMemcpyAsync(p->d_delay[slot], h, sizeof(double) * 2 * S, hipMemcpyHostToDevice, st);
+    const size_t bytes = sizeof(double) * 2 * S + (h_coarse ? sizeof(int32_t) * S : 0);
+    if (h_coarse) std::memcpy(h + sizeof(double) * 2 * S, h_coarse, sizeof(int32_t) * S);
+    hipError_t e = hipMemcpyAsync(p->d_stage[slot], h, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(delays)");
     e = hipEventRecord(p->ring_ev[slot], st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord(delays)");
     p->ring_used[slot] = true;
-    *d_out = p->d_delay[slot];
+    *d_delays = (const double*)p->d_stage[slot];
+    *d_coarse = h_coarse ? (const int32_t*)(p->d_stage[slot] + sizeof(double) * 2 * S) : nullptr;
     return COBALT_OK;
 }
 
-int run_fstage(cobalt_plan* p, const void* d_in, const double* d_delays, void* d_chan, hipStream_t st) {
+// Flagged channel samples of this block (null when nothing can be flagged: no flags given
+// and the carried row flags are known to be clear).
+int run_flags(cobalt_plan* p, const uint32_t* d_flags, int64_t row_len, const int32_t* d_coarse, hipStream_t st,
+              const uint32_t** cflag) {
+    const Sizes& z = p->z;
+    *cflag = nullptr;
+    if (z.n_c == 0 || (!d_flags && !p->flag_dirty)) return COBALT_OK;
+    FlagArgs a{};
+    a.flags = d_flags;
+    a.flag_words = (row_len + 31) / 32;
+    a.coarse = d_coarse;
+    a.hist_old = p->d_rowhist[p->rowhist_cur];
+    a.hist_new = p->d_rowhist[p->rowhist_cur ^ 1];
+    a.cflag = p->d_cflag;
+    a.S = (int)z.S;
+    a.SB = (int)z.SB;
+    a.n_c = (int)z.n_c;
+    a.n_words = (int)z.n_words;
+    hipError_t e = launch_chanflags(a, st);
+    if (e != hipSuccess) return hip_fail(e, "flag launch");
+    p->rowhist_cur ^= 1;
+    // the new carried rows are the last T-1 rows of [old rows, block rows]: clear when no
+    // flags came in and the block alone spans them
+    p->flag_dirty = d_flags != nullptr || (p->flag_dirty && z.n_c < kHistRows);
+    *cflag = p->d_cflag;
+    return COBALT_OK;
+}
+
+int run_fstage(cobalt_plan* p, const void* d_in, int64_t row_len, const double* d_delays, const int32_t* d_coarse,
+               const uint32_t* cflag, void* d_chan, hipStream_t st) {
     const Sizes& z = p->z;
     if (z.n_c == 0) return COBALT_OK;       // empty block: nothing to filter, history unchanged
     FArgs a{};
@@ -223,7 +275,11 @@ int run_fstage(cobalt_plan* p, const void* d_in, const double* d_delays, void* d
     a.bscale = p->d_bscale;
     a.f_sb = p->d_fsb;
     a.delays = d_delays;
+    a.coarse = d_coarse;
+    a.cflag = cflag;
     a.N = z.N;
+    a.row_len = row_len;
+    a.n_words = (int)z.n_words;
     a.S = (int)z.S;
     a.SB = (int)z.SB;
     a.M = (int)z.M;
@@ -231,7 +287,8 @@ int run_fstage(cobalt_plan* p, const void* d_in, const double* d_delays, void* d
     a.pitch = (int)z.pitch;
     a.n_chunks = (int)((z.pitch + kFChunk - 1) / kFChunk);
     a.n_kb = (int)(z.pitch / kKBlock);
-    a.df = p->cfg.sample_rate_hz / kC;
+    a.df = p->cfg.sample_rate_hz / (double)z.C;
+    a.C = (int)z.C;
     hipError_t e = launch_fstage(p->cfg.sample_type, p->cfg.x_mode, a, (int)z.streams, st);
     if (e != hipSuccess) return hip_fail(e, "F-stage launch");
     p->hist_cur ^= 1;
@@ -248,7 +305,7 @@ int run_xstage(cobalt_plan* p, const void* d_chan, void* d_vis, hipStream_t st) 
     a.S = (int)z.S;
     a.n_c = (int)z.n_c;
     a.pitch = (int)z.pitch;
-    a.n_chan = (int)(z.SB * kC);
+    a.n_chan = (int)(z.SB * z.C);
     a.n_blocks8 = (int)((z.M + 7) / 8);
     a.n_kb = (int)(z.pitch / kKBlock);
     a.out_scale = std::ldexp(1.0f, -2 * p->cfg.fp16_prescale_log2);
@@ -307,12 +364,15 @@ int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) {
     p->d_chan = q;                q += round_up(z.chan_bytes, 256);
     p->d_hist[0] = q;             q += round_up(z.hist_bytes, 256);
     p->d_hist[1] = q;             q += round_up(z.hist_bytes, 256);
-    p->d_fir = (float*)q;         q += round_up((int64_t)kT * kC * 4, 256);
-    p->d_bscale = (float*)q;      q += round_up(kC * 4, 256);
+    p->d_rowhist[0] = (uint32_t*)q; q += round_up(z.rowhist_bytes, 256);
+    p->d_rowhist[1] = (uint32_t*)q; q += round_up(z.rowhist_bytes, 256);
+    p->d_cflag = (uint32_t*)q;    q += round_up(z.cflag_bytes, 256);
+    p->d_fir = (float*)q;         q += round_up(kT * z.C * 4, 256);
+    p->d_bscale = (float*)q;      q += round_up(z.C * 4, 256);
     p->d_fsb = (double*)q;        q += round_up(z.SB * 8, 256);
-    for (int i = 0; i < kRing; ++i) { p->d_delay[i] = (double*)q; q += round_up(z.S * 16, 256); }
+    for (int i = 0; i < kRing; ++i) { p->d_stage[i] = q; q += z.stage_bytes; }
 
-    e = hipHostMalloc((void**)&p->h_delay, sizeof(double) * 2 * z.S * kRing, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&p->h_stage, (size_t)z.stage_bytes * kRing, hipHostMallocDefault);
     if (e != hipSuccess) { free_plan(p); (void)hipGetLastError(); return fail(COBALT_ENOMEM, "hipHostMalloc failed"); }
     for (int i = 0; i < kRing; ++i) {
         e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
@@ -322,17 +382,17 @@ int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) {
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipEventCreate"); }
 
     // tables: FIR, bandpass x mode scale (2^k, requant gain, or 1), subband frequencies
-    float bscale[kC];
+    float bscale[256];
     const double mode_scale = cfg->x_mode == COBALT_X_FP16_SPLIT ? std::ldexp(1.0, cfg->fp16_prescale_log2)
                               : cfg->x_mode == COBALT_X_INT8   ? (double)cfg->requant_gain
                                                                : 1.0;
-    for (int c = 0; c < kC; ++c) bscale[c] = (float)((cfg->h_bandpass ? (double)cfg->h_bandpass[c] : 1.0) * mode_scale);
-    e = hipMemcpy(p->d_fir, cfg->h_fir, sizeof(float) * kT * kC, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_bscale, bscale, sizeof bscale, hipMemcpyHostToDevice);
+    for (int c = 0; c < z.C; ++c) bscale[c] = (float)((cfg->h_bandpass ? (double)cfg->h_bandpass[c] : 1.0) * mode_scale);
+    e = hipMemcpy(p->d_fir, cfg->h_fir, sizeof(float) * kT * z.C, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_bscale, bscale, sizeof(float) * z.C, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_fsb, cfg->h_subband_freq_hz, sizeof(double) * z.SB, hipMemcpyHostToDevice);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "table upload"); }
-    // FIR history starts at zero (no samples before the first block)
-    e = launch_zero_fill(p->d_hist[0], round_up(z.hist_bytes, 256) * 2, nullptr);
+    // FIR history starts at zero (no samples before the first block), its rows unflagged
+    e = launch_zero_fill(p->d_hist[0], round_up(z.hist_bytes, 256) * 2 + round_up(z.rowhist_bytes, 256) * 2, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "history init"); }
     *out = p;
@@ -350,17 +410,37 @@ int cobalt_plan_query(const cobalt_plan* p, cobalt_plan_info* info) {
     info->chan_bytes = z.chan_bytes;
     info->vis_bytes = z.vis_bytes;
     info->workspace_bytes = z.workspace_bytes;
-    info->useful_cmacs = z.B * 4 * z.SB * kC * z.n_c;
+    info->useful_cmacs = z.B * 4 * z.SB * z.C * z.n_c;
     return COBALT_OK;
 }
 
-static int do_fx(cobalt_plan* p, const void* d_in, const double* h_delays, void* d_chan, void* d_vis, void* stream) {
+static int do_fx(cobalt_plan* p, const void* d_in, const double* h_delays, const cobalt_block_ext* ext, void* d_chan,
+                 void* d_vis, void* stream) {
     g_last_error.clear();
     if (!p) return fail(COBALT_EINVAL, "plan is NULL");
     if ((!d_in && p->z.input_bytes > 0) || !h_delays) return fail(COBALT_EINVAL, "d_in or h_delays is NULL");
     if (!d_chan && !d_vis) return fail(COBALT_EINVAL, "output pointer is NULL");
     if (((uintptr_t)d_in | (uintptr_t)d_chan | (uintptr_t)d_vis) % 16)
         return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
+    const Sizes& z = p->z;
+    int64_t row_len = z.N;
+    const int32_t* h_coarse = nullptr;
+    const uint32_t* d_flags = nullptr;
+    int32_t* d_weights = nullptr;
+    if (ext) {
+        if (ext->row_samples != 0) {
+            if (ext->row_samples < z.N) return fail(COBALT_EINVAL, "row_samples (%lld) is below N (%lld)",
+                                                    (long long)ext->row_samples, (long long)z.N);
+            if (ext->row_samples > ((int64_t)1 << 40)) return fail(COBALT_EINVAL, "row_samples too large");
+            row_len = ext->row_samples;
+        }
+        h_coarse = ext->h_coarse_offset;
+        d_flags = ext->d_flags;
+        d_weights = ext->d_weights;
+        if (d_flags && z.C != kC) return fail(COBALT_EUNSUPPORTED, "lost-sample flags are built for %d channels only", kC);
+        if (((uintptr_t)d_flags | (uintptr_t)d_weights) % 4)
+            return fail(COBALT_EINVAL, "d_flags and d_weights must be 4-byte aligned");
+    }
     CallLock lock(p);
     if (!lock.owns()) return fail(COBALT_EBUSY, "plan is in use by another host thread");
     DeviceGuard dg(p->device);
@@ -369,11 +449,19 @@ static int do_fx(cobalt_plan* p, const void* d_in, const double* h_delays, void*
     int rc = begin_call(p, st);
     if (rc) return rc;
     const double* d_delays = nullptr;
-    rc = stage_delays(p, h_delays, st, &d_delays);
+    const int32_t* d_coarse = nullptr;
+    rc = stage_block(p, h_delays, h_coarse, row_len - z.N, st, &d_delays, &d_coarse);
+    if (rc) return rc;
+    const uint32_t* cflag = nullptr;
+    rc = run_flags(p, d_flags, row_len, d_coarse, st, &cflag);
     if (rc) return rc;
     void* chan = d_chan ? d_chan : p->d_chan;
-    rc = run_fstage(p, d_in, d_delays, chan, st);
+    rc = run_fstage(p, d_in, row_len, d_delays, d_coarse, cflag, chan, st);
     if (rc) return rc;
+    if (d_weights) {
+        hipError_t e = launch_weights(cflag, d_weights, (int)z.S, (int)z.SB, (int)z.n_c, (int)z.n_words, st);
+        if (e != hipSuccess) return hip_fail(e, "weights launch");
+    }
     if (d_vis) {
         rc = run_xstage(p, chan, d_vis, st);
         if (rc) return rc;
@@ -383,12 +471,111 @@ static int do_fx(cobalt_plan* p, const void* d_in, const double* h_delays, void*
 
 int cobalt_correlate(cobalt_plan* p, const void* d_in, const double* h_delays, void* d_vis, void* stream) {
     if (!d_vis) { g_last_error = "d_vis is NULL"; return COBALT_EINVAL; }
-    return do_fx(p, d_in, h_delays, nullptr, d_vis, stream);
+    return do_fx(p, d_in, h_delays, nullptr, nullptr, d_vis, stream);
 }
 
 int cobalt_channelize(cobalt_plan* p, const void* d_in, const double* h_delays, void* d_chan, void* stream) {
     if (!d_chan) { g_last_error = "d_chan is NULL"; return COBALT_EINVAL; }
-    return do_fx(p, d_in, h_delays, d_chan, nullptr, stream);
+    return do_fx(p, d_in, h_delays, nullptr, d_chan, nullptr, stream);
+}
+
+int cobalt_correlate_ex(cobalt_plan* p, const void* d_in, const double* h_delays, const cobalt_block_ext* ext, void* d_vis,
+                        void* stream) {
+    if (!d_vis) { g_last_error = "d_vis is NULL"; return COBALT_EINVAL; }
+    return do_fx(p, d_in, h_delays, ext, nullptr, d_vis, stream);
+}
+
+int cobalt_channelize_ex(cobalt_plan* p, const void* d_in, const double* h_delays, const cobalt_block_ext* ext, void* d_chan,
+                         void* stream) {
+    if (!d_chan) { g_last_error = "d_chan is NULL"; return COBALT_EINVAL; }
+    return do_fx(p, d_in, h_delays, ext, d_chan, nullptr, stream);
+}
+
+// ---- beamformer ----
+static int check_beam(const cobalt_plan* p, const cobalt_beam_params* bp, const void* coh, const void* volt, const void* inc) {
+    const Sizes& z = p->z;
+    if (!bp) return fail(COBALT_EINVAL, "beam parameters are NULL");
+    if (p->cfg.x_mode != COBALT_X_FP16_SPLIT) return fail(COBALT_EUNSUPPORTED, "the beamformer needs an FP16-split plan");
+    if (z.S > 56) return fail(COBALT_EUNSUPPORTED, "the beamformer supports up to 56 stations (got %lld)", (long long)z.S);
+    if (bp->n_beams < 1) return fail(COBALT_EINVAL, "n_beams must be >= 1 (got %d)", bp->n_beams);
+    if (bp->n_stokes != 1 && bp->n_stokes != 4) return fail(COBALT_EINVAL, "n_stokes must be 1 or 4 (got %d)", bp->n_stokes);
+    if (bp->reserved0 != 0) return fail(COBALT_EINVAL, "reserved0 must be 0");
+    const int ni = bp->n_int;
+    const bool pow2 = ni >= 1 && ni <= 32 && (ni & (ni - 1)) == 0;
+    if (!(pow2 || (ni > 32 && ni % 32 == 0))) return fail(COBALT_EINVAL, "n_int must be a power of two <= 32 or a multiple of 32 (got %d)", ni);
+    if (z.n_c % ni != 0) return fail(COBALT_EINVAL, "n_int (%d) must divide N_c (%lld)", ni, (long long)z.n_c);
+    if (!bp->d_beam_dtau || (uintptr_t)bp->d_beam_dtau % 8) return fail(COBALT_EINVAL, "d_beam_dtau is NULL or misaligned");
+    if (!coh && !volt && !inc) return fail(COBALT_EINVAL, "no output requested");
+    if (((uintptr_t)coh | (uintptr_t)volt | (uintptr_t)inc) % 16) return fail(COBALT_EINVAL, "outputs must be 16-byte aligned");
+    return COBALT_OK;
+}
+
+static int run_beam(cobalt_plan* p, const void* chan, const cobalt_beam_params* bp, void* coh, void* volt, void* inc,
+                    hipStream_t st) {
+    const Sizes& z = p->z;
+    BeamArgs a{};
+    a.chan = chan;
+    a.chan_stride = z.chan_stride;
+    a.f_sb = p->d_fsb;
+    a.dtau = bp->d_beam_dtau;
+    a.coherent = coh;
+    a.voltages = volt;
+    a.incoherent = inc;
+    a.df = p->cfg.sample_rate_hz / (double)z.C;
+    a.C = (int)z.C;
+    a.S = (int)z.S;
+    a.NB = bp->n_beams;
+    a.n_c = (int)z.n_c;
+    a.n_kb = (int)(z.pitch / kKBlock);
+    a.n_chan = (int)(z.SB * z.C);
+    a.n_int = bp->n_int;
+    a.n_stokes = bp->n_stokes;
+    a.vscale = std::ldexp(1.0f, -p->cfg.fp16_prescale_log2);
+    if (z.n_c == 0) return COBALT_OK;
+    hipError_t e = launch_beamformer(a, st);
+    if (e != hipSuccess) return hip_fail(e, "beamformer launch");
+    return COBALT_OK;
+}
+
+int cobalt_beamform(cobalt_plan* p, const void* d_in, const double* h_delays, const cobalt_beam_params* bp, void* d_coherent,
+                    void* d_voltages, void* d_incoherent, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    int rc = check_beam(p, bp, d_coherent, d_voltages, d_incoherent);
+    if (rc) return rc;
+    if ((!d_in && p->z.input_bytes > 0) || !h_delays) return fail(COBALT_EINVAL, "d_in or h_delays is NULL");
+    if ((uintptr_t)d_in % 16) return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
+    CallLock lock(p);
+    if (!lock.owns()) return fail(COBALT_EBUSY, "plan is in use by another host thread");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    rc = begin_call(p, st);
+    if (rc) return rc;
+    const double* d_delays = nullptr;
+    const int32_t* d_coarse = nullptr;
+    rc = stage_block(p, h_delays, nullptr, 0, st, &d_delays, &d_coarse);
+    if (rc) return rc;
+    const uint32_t* cflag = nullptr;
+    rc = run_flags(p, nullptr, p->z.N, nullptr, st, &cflag);
+    if (rc) return rc;
+    rc = run_fstage(p, d_in, p->z.N, d_delays, nullptr, cflag, p->d_chan, st);
+    if (rc) return rc;
+    rc = run_beam(p, p->d_chan, bp, d_coherent, d_voltages, d_incoherent, st);
+    if (rc) return rc;
+    return end_call(p, st);
+}
+
+int cobalt_beamform_channelized(cobalt_plan* p, const void* d_chan, const cobalt_beam_params* bp, void* d_coherent,
+                                void* d_voltages, void* d_incoherent, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    int rc = check_beam(p, bp, d_coherent, d_voltages, d_incoherent);
+    if (rc) return rc;
+    if ((!d_chan && p->z.chan_bytes > 0) || (uintptr_t)d_chan % 16) return fail(COBALT_EINVAL, "d_chan is NULL or misaligned");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    return run_beam(p, d_chan, bp, d_coherent, d_voltages, d_incoherent, (hipStream_t)stream);
 }
 
 // Stateless with respect to the plan (reads only its immutable sizes): ordered by the
@@ -414,7 +601,9 @@ int cobalt_reset_history(cobalt_plan* p, void* stream) {
     int rc = begin_call(p, st);
     if (rc) return rc;
     hipError_t e = launch_zero_fill(p->d_hist[p->hist_cur], round_up(p->z.hist_bytes, 256), st);
+    if (e == hipSuccess) e = launch_zero_fill(p->d_rowhist[p->rowhist_cur], round_up(p->z.rowhist_bytes, 256), st);
     if (e != hipSuccess) return hip_fail(e, "history reset");
+    p->flag_dirty = false;
     return end_call(p, st);
 }
 
@@ -429,7 +618,7 @@ static int gains_call(cobalt_plan* p, const void* a0, const void* a1, const void
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
     hipStream_t st = (hipStream_t)stream;
-    const int n_chan = (int)(p->z.SB * kC), S = (int)p->z.S;
+    const int n_chan = (int)(p->z.SB * p->z.C), S = (int)p->z.S;
     hipError_t e = adjoint ? launch_apply_gains_adjoint(a0, a1, a2, out, n_chan, S, st)
                            : launch_apply_gains(a0, a1, out, n_chan, S, st);
     if (e != hipSuccess) return hip_fail(e, adjoint ? "gain adjoint launch" : "gain launch");

@@ -260,3 +260,42 @@ def float_channelised(seed: int, n_chan: int, M: int, n_c: int, sigma: float = 8
     rng = np.random.default_rng([seed, 0xF1])
     v = (rng.standard_normal((n_chan, M, n_c, 2)) * sigma).astype(np.float32)
     return v[..., 0].astype(np.float64) + 1j * v[..., 1].astype(np.float64)
+
+
+def guarded_rows(w: "Workload", block: int, guard: int) -> np.ndarray:
+    """Input rows of ``N + guard`` samples per stream [S, P, SB, N + guard, 2] (storage dtype),
+    for blocks read through per-station coarse-delay windows; drawn like ``Workload.block``
+    with the guard samples appended to each stream."""
+    out = np.empty((w.S, w.P, w.SB, w.N + guard, 2), storage_dtype(w.sample_type))
+    for s in range(w.S):
+        for p in range(w.P):
+            for sb in range(w.SB):
+                out[s, p, sb] = gaussian_stream(w.seed, block, s, p, sb, w.N + guard, w.sigma, w.sample_type)
+    return out
+
+
+def lost_sample_flags(seed: int, S: int, SB: int, n: int, packet: int = 16, p_packet: float = 0.002,
+                      p_sample: float = 0.0005, clean_stations=()) -> np.ndarray:
+    """Lost-sample flags bool [S, SB, n]: whole packets of ``packet`` consecutive samples lost
+    with probability ``p_packet`` each (packets aligned to multiples of ``packet``, as station
+    packets carry fixed runs of time samples) plus isolated lost samples with probability
+    ``p_sample``; the stations in ``clean_stations`` lose nothing."""
+    rng = np.random.default_rng([seed, 0xF1A6])
+    n_pk = (n + packet - 1) // packet
+    lost_pk = rng.random((S, SB, n_pk)) < p_packet
+    flags = np.repeat(lost_pk, packet, axis=-1)[..., :n]
+    flags |= rng.random((S, SB, n)) < p_sample
+    for s in clean_stations:
+        flags[s] = False
+    return flags
+
+
+def pack_flags(flags: np.ndarray) -> np.ndarray:
+    """bool [..., n] -> uint32 words [..., ceil(n / 32)]: bit k of word w = sample 32 w + k."""
+    f = np.asarray(flags, bool)
+    n = f.shape[-1]
+    words = (n + 31) // 32
+    pad = np.zeros(f.shape[:-1] + (words * 32,), bool)
+    pad[..., :n] = f
+    bits = pad.reshape(f.shape[:-1] + (words, 32)).astype(np.uint64)
+    return np.sum(bits << np.arange(32, dtype=np.uint64), axis=-1).astype(np.uint32)

@@ -51,7 +51,8 @@ def test_estimate_bytes_of_the_16bit_share():
     # channelised FP16 hi/lo planes dominate: 64 SB x 64 ch x 2 x 152 x 3072 x 4 B
     chan = 64 * 64 * 2 * 152 * 3072 * 4
     hist = 2 * 64 * 152 * 960 * 4          # two FIR-history buffers of (T-1)*C ci16 samples
-    assert chan + hist <= n <= chan + hist + 2**20
+    cflag = 76 * 64 * (3072 // 32) * 4      # flagged-channel-sample bits per station and subband
+    assert chan + hist + cflag <= n <= chan + hist + cflag + 2**20
 
 
 @pytest.mark.parametrize("over,code", [
@@ -102,3 +103,13 @@ def test_plan_requires_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_LIB", None)
     with pytest.raises(RuntimeError, match="not built"):
         binding.load_library()
+
+
+@pytest.mark.parametrize("args", [(2**30, 0, 4, 1.0), (2**30, 65, 4, 1.0), (2**30, 2, 0, 1.0), (2**30, 2, 4, 0.0)])
+def test_service_rejects_bad_arguments_before_touching_a_gpu(args):
+    import ctypes as ct
+    lib = _lib()
+    out = ct.c_void_p(None)
+    rc = lib.cobalt_service_create(ct.c_size_t(args[0]), args[1], args[2], ct.c_double(args[3]), ct.byref(out))
+    assert rc == binding.EINVAL and not out.value
+    assert lib.cobalt_service_last_error().decode()

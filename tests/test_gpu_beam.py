@@ -1,0 +1,145 @@
+"""GPU parity of the beamformer (coherent voltages and Stokes, incoherent Stokes) against the
+FP64 oracle ``oracle.beam``, through the C ABI, at 256 channels.
+
+Tolerances (FP16-split operands, FP32 accumulation; the channelised data carry at most
+5e-6 rms + 2e-6 |Z| error, the weights 2^-22): voltages max |dB| <= 2e-5 rms(B); Stokes
+|dS| <= 2e-5 I + 1e-6 mean(I) per element (a relative voltage error e moves I, Q, U, V by
+at most about 2e I).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import beam as ob
+from paper_1801_04834_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+C = 256
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _work(S, SB, n_c, seed, st=synth.CI16, mode=synth.X_FP16_SPLIT):
+    return synth.Workload(name="beam", S=S, SB=SB, sample_type=st, x_mode=mode, N=C * n_c, C=C, sigma=64.0, seed=seed,
+                          delay_spread_s=2e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5)
+
+
+def _oracle(w, blocks, dtau, n_stokes, n_int):
+    hist = np.zeros((w.S, 2, w.SB, 15 * C), np.complex128)
+    outs = []
+    for k, x in enumerate(blocks):
+        o = ob.beamform_block(synth.to_complex(x), hist, w.fir(), w.bandpass(), w.subband_freqs(), synth.SAMPLE_RATE_HZ,
+                              w.delays(k), dtau, C, 16, which="IQUV" if n_stokes == 4 else "I", n_int=n_int)
+        hist = o["history"]
+        outs.append(o)
+    return outs
+
+
+def _check(label, coh, volt, inc, o):
+    B = o["beams"]
+    Vg = volt[..., 0].astype(np.float64) + 1j * volt[..., 1]
+    rms = np.sqrt(np.mean(np.abs(B) ** 2))
+    ev = float(np.max(np.abs(Vg - B))) / rms
+    res = {"voltages": ev}
+    for name, got, want in (("coherent", coh, o["coherent"]), ("incoherent", inc, o["incoherent"])):
+        I = want[..., 0:1, :]
+        err = np.abs(got.astype(np.float64) - want)
+        bound = 2e-5 * np.abs(I) + 1e-6 * np.mean(np.abs(I))
+        res[name] = float(np.max(err / (np.abs(I) + np.mean(np.abs(I)))))
+        assert np.all(err <= bound), f"{label}: {name} off, worst {res[name]:.3e}"
+    _say(f"  {label}: " + "  ".join(f"{k} {v:.2e}" for k, v in res.items()))
+    assert ev <= 2e-5, f"{label}: voltages off by {ev:.3e} rms"
+
+
+@pytest.mark.parametrize("S,NB,n_c,n_int,n_stokes", [(6, 37, 40, 1, 4), (6, 37, 40, 8, 4), (13, 130, 64, 64, 1),
+                                                     (48, 32, 96, 32, 4), (1, 1, 33, 1, 4)])
+def test_beamformer_matches_oracle(S, NB, n_c, n_int, n_stokes):
+    from paper_1801_04834_amd import binding
+    SB = 2
+    seed = 2700 + S + NB + n_c
+    w = _work(S, SB, n_c, seed)
+    rng = np.random.default_rng(seed)
+    dtau = rng.uniform(-4e-6, 4e-6, (NB, S))
+    _say(f"CASE beam S={S} NB={NB} n_c={n_c} n_int={n_int} n_stokes={n_stokes} seed={seed}")
+    blocks = [w.block(k) for k in range(2)]
+    outs = _oracle(w, blocks, dtau, n_stokes, n_int)
+    with binding.plan_for(w) as plan, binding.plan_for(w) as plan2:
+        cs, vs, isz = plan.beam_shapes(NB, n_stokes, n_int)
+        dt = torch.from_numpy(dtau).cuda()
+        for k in range(2):
+            x = torch.from_numpy(blocks[k]).cuda()
+            coh = torch.full(cs, np.nan, dtype=torch.float32, device="cuda")
+            volt = torch.full(vs, np.nan, dtype=torch.float32, device="cuda")
+            inc = torch.full(isz, np.nan, dtype=torch.float32, device="cuda")
+            plan.beamform(x, w.delays(k), dt, n_stokes, n_int, coherent=coh, voltages=volt, incoherent=inc)
+            # the same block through the F stage + the stateless beamformer on a second plan
+            chan = plan2.channelize(x, w.delays(k))
+            coh2 = torch.full(cs, np.nan, dtype=torch.float32, device="cuda")
+            plan2.beamform_channelized(chan, dt, n_stokes, n_int, coherent=coh2)
+            torch.cuda.synchronize()
+            assert torch.equal(coh, coh2)
+            _check(f"block {k}", coh.cpu().numpy(), volt.cpu().numpy(), inc.cpu().numpy(), outs[k])
+
+
+def test_pointed_beam_on_a_tone():
+    """A bin-centred sky tone reaching station s tau_s late: the beam with dtau = tau has
+    I = 2 S^2 |z|^2 in the tone's channel (z = one station's aligned channel value), the beam
+    at the centre much less, and the incoherent beam 2 S |z|^2."""
+    from paper_1801_04834_amd import binding
+    S, n_c, A, c0 = 8, 32, 200.0, 91
+    f_s = synth.SAMPLE_RATE_HZ
+    w = synth.Workload(name="beamtone", S=S, SB=1, sample_type=synth.CF32, x_mode=synth.X_FP16_SPLIT, N=C * n_c, C=C,
+                       sigma=0.0, seed=3, f_sb0=768 * f_s, fp16_prescale_log2=0)
+    F = 768 * f_s + (c0 - C / 2) * f_s / C
+    taus = np.random.default_rng(9).uniform(-2e-6, 2e-6, S)
+    _say(f"CASE beam tone c0={c0}")
+    n = np.arange(2 * w.N)
+    x = np.zeros((S, 2, 1, 2 * w.N, 2), np.float32)
+    for s in range(S):
+        v = A * np.exp(2j * np.pi * ((c0 - C // 2) / C * n - F * taus[s]))
+        x[s, :, 0, :, 0] = v.real
+        x[s, :, 0, :, 1] = v.imag
+    with binding.plan_for(w) as plan:
+        dt = torch.from_numpy(np.stack([taus, np.zeros(S)])).cuda()
+        cs, vs, isz = plan.beam_shapes(2, 4, n_c)
+        coh = torch.empty(cs, dtype=torch.float32, device="cuda")
+        inc = torch.empty(isz, dtype=torch.float32, device="cuda")
+        for k in range(2):                   # the second block is past the FIR warm-up
+            xb = torch.from_numpy(np.ascontiguousarray(x[..., k * w.N:(k + 1) * w.N, :])).cuda()
+            plan.beamform(xb, np.zeros((S, 2)), dt, 4, n_c, coherent=coh, incoherent=inc)
+        torch.cuda.synchronize()
+        one = n_c * (A * float(np.sum(w.fir().astype(np.float64)))) ** 2
+        I = coh.cpu().numpy()[0, c0, :, 0, 0]
+        _say(f"  pointed {I[0] / (2 * S * S * one):.6f}  centre {I[1] / (2 * S * S * one):.4f}")
+        assert abs(I[0] - 2 * S * S * one) <= 2e-5 * I[0]
+        assert I[1] < 0.6 * I[0]
+        assert abs(inc.cpu().numpy()[0, c0, 0, 0] - 2 * S * one) <= 2e-5 * 2 * S * one
+
+
+def test_beamformer_rejects_bad_parameters():
+    from paper_1801_04834_amd import binding
+    w = _work(4, 1, 40, 2800)
+    _say("CASE beam invalid")
+    dt = torch.zeros((3, 4), dtype=torch.float64, device="cuda")
+    with binding.plan_for(w) as plan:
+        chan = plan.empty_chan()
+        coh = torch.empty(plan.beam_shapes(3, 4, 8)[0], dtype=torch.float32, device="cuda")
+        for n_int in (3, 16):                # 3 is no power of two, 16 does not divide 40
+            out = torch.empty(plan.beam_shapes(3, 4, n_int)[0], dtype=torch.float32, device="cuda")
+            with pytest.raises(binding.CobaltError) as ei:
+                plan.beamform_channelized(chan, dt, 4, n_int, coherent=out)
+            assert ei.value.code == binding.EINVAL
+        with pytest.raises(binding.CobaltError) as ei:
+            plan.beamform_channelized(chan, dt, 4, 8)          # no output
+        assert ei.value.code == binding.EINVAL
+    with binding.plan_for(_work(4, 1, 40, 2801, mode=synth.X_FP32)) as plan:
+        with pytest.raises(binding.CobaltError) as ei:
+            plan.beamform_channelized(plan.empty_chan(), dt, 4, 8, coherent=coh)
+        assert ei.value.code == binding.EUNSUPPORTED
