@@ -12,6 +12,7 @@ when timing starts.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,6 +30,39 @@ HBM_PEAK_GBS = 8000.0
 FP16_MFMA_PEAK_TFLOPS = 2516.6       # dense fp16 MFMA, 256 CU x 2.4 GHz x 4096 flop/clk
 INT8_MFMA_PEAK_TOPS = 5033.2
 FP32_VALU_PEAK_TFLOPS = 157.3        # published vector FP32 (dual-issue/packed)
+# FP32 vector FMA without packed math (these kernels are built with packed FP32 disabled):
+# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_VALU_NOPACK_TFLOPS = 78.6
+# F-stage arithmetic per complex sample: FIR 16 taps x 2 FMA (64 flop), 64-point FFT
+# (5 N log2 N / N = 30 flop), phase rotation 6 + bandpass 2 flop
+F_FLOP_PER_SAMPLE = 102
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_1801_04834_amd", "csrc")
+
+
+def source_digest(files):
+    """sha256 over the kernel's source files (csrc/), as recorded beside the counters."""
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch (read + write) of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's readings), or None when
+    there is none or the kernel's sources changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            entry = json.load(fh)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if entry.get("source_sha256") != source_digest(entry["sources"]):
+        return None
+    return int(entry["read_bytes"] + entry["write_bytes"])
 
 
 def log(msg):
@@ -50,6 +84,8 @@ def parse():
                     help="steps of the coarse-delay + lost-sample-flag path (0: skip)")
     ap.add_argument("--beam-steps", type=int, default=3,
                     help="steps of the beamformer workload (48 stations, 61 subbands, 256 channels, 127 beams; 0: skip)")
+    ap.add_argument("--gains-steps", type=int, default=3,
+                    help="steps of the differentiable gain-applied correlator (48 stations, 16 subbands; 0: skip)")
     ap.add_argument("--service", action="store_true",
                     help="streaming service run instead: three concurrent observations (24/48/76 stations, "
                          "32/64/128 subbands, ci16/ci16/ci8), Poisson block arrivals, HBM-budget admission")
@@ -189,6 +225,40 @@ def time_beamformer(torch, binding, synth, steps, device):
     plan.close()
     del x, chan, coh, inc
     return w, NB, n_int, f_ms, b_ms
+
+
+def time_gains(torch, binding, synth, steps, device):
+    """Differentiable gain-applied correlator on 48 stations x 2 pol, 16 subbands x 64 channels:
+    one correlated block, then per step the gain forward (V' = g_a conj(g_b) V0) and the
+    hand-written adjoint (dL/dg for an upstream gradient of V's shape)."""
+    w = synth.Workload(name="gains_48", S=48, SB=16, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, sigma=64.0,
+                       seed=1809, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5)
+    plan = binding.plan_for(w)
+    x = make_input(w, torch, device)
+    vis0 = torch.view_as_complex(plan.correlate(x, w.delays(0)))
+    rng = np.random.default_rng(1810)
+    g = rng.uniform(0.5, 1.5, plan.gains_shape) * np.exp(1j * rng.uniform(-np.pi, np.pi, plan.gains_shape))
+    gains = torch.from_numpy(g.astype(np.complex64)).to(device)
+    grad = torch.randn(vis0.shape, dtype=torch.complex64, device=device)
+    out = torch.empty_like(vis0)
+    gg = torch.empty_like(gains)
+    plan.apply_gains(vis0, gains, out=out)
+    plan.apply_gains_adjoint(vis0, gains, grad, out=gg)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        plan.apply_gains(vis0, gains, out=out)
+        ev[k][1].record()
+        plan.apply_gains_adjoint(vis0, gains, grad, out=gg)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    adj = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    n_ent = vis0.numel()
+    plan.close()
+    del x
+    return w, n_ent, fwd, adj
 
 
 def block_latency(torch, plan, x, delays, n):
@@ -402,12 +472,22 @@ def main():
         x_mfma_tflops = cmacs * 8 / (x_ms_avg * 1e-3) / 1e12
         x_peak, x_unit = FP32_VALU_PEAK_TFLOPS, "TFLOP/s"
     x_bytes = w.SB * w.C * w.M * w.n_c * chan_b
-    f_roof = {"bound": "hbm", "achieved": round(f_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(f_gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "fstage",
-              "ms": round(f_ms_avg, 4), "algorithmic_bytes": f_bytes}
+    f_kernel = f"fstage_kernel<{w.sample_type}, {w.x_mode}, {w.C}>"
+    x_kernel = f"xstage_mfma_kernel<{w.x_mode}, {(w.M + 31) // 32}>" if w.x_mode != synth.X_FP32 else "xstage_fp32_kernel"
+    if w.x_mode == synth.X_INT8:
+        # 4 B per sample against ~100 flop: the 8-bit F stage is bound by vector arithmetic
+        f_tf = samples * F_FLOP_PER_SAMPLE / (f_ms_avg * 1e-3) / 1e12
+        f_roof = {"bound": "alu", "achieved": round(f_tf, 1), "peak": FP32_VALU_NOPACK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": round(f_tf / FP32_VALU_NOPACK_TFLOPS, 4), "traffic": measured_traffic(f_kernel),
+                  "kernel": f_kernel, "ms": round(f_ms_avg, 4), "algorithmic_bytes": f_bytes,
+                  "hbm_gbs": round(f_gbs, 1)}
+    else:
+        f_roof = {"bound": "hbm", "achieved": round(f_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(f_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f_kernel), "kernel": f_kernel,
+                  "ms": round(f_ms_avg, 4), "algorithmic_bytes": f_bytes}
     x_roof = {"bound": "mfma" if w.x_mode != synth.X_FP32 else "alu", "achieved": round(x_mfma_tflops, 1),
-              "peak": x_peak, "unit": x_unit, "frac": round(x_mfma_tflops / x_peak, 4), "traffic": None,
-              "kernel": "xstage", "ms": round(x_ms_avg, 4),
+              "peak": x_peak, "unit": x_unit, "frac": round(x_mfma_tflops / x_peak, 4),
+              "traffic": measured_traffic(x_kernel), "kernel": x_kernel, "ms": round(x_ms_avg, 4),
               "operand_gbs": round(x_bytes / (x_ms_avg * 1e-3) / 1e9, 1)}
     dominant = f_roof if f_ms_avg >= x_ms_avg else x_roof
     other = x_roof if dominant is f_roof else f_roof
@@ -446,10 +526,20 @@ def main():
                 "beam_tcmacs": round(cmac_b / (b_ms * 1e-3) / 1e12, 3),
                 "real_time_factor": round(bw.N / synth.SAMPLE_RATE_HZ / ((float(np.mean(bf_ms)) + b_ms) * 1e-3), 2),
                 "roofline": {"bound": "mfma", "achieved": round(mfma_tf, 1), "peak": FP16_MFMA_PEAK_TFLOPS,
-                             "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                             "kernel": "beam_kernel"}}
+                             "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4),
+                             "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}>"),
+                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}>"}}
         log(f"bench: beamformer F {np.mean(bf_ms):.3f} ms + beams {b_ms:.3f} ms "
             f"({beam['beam_tcmacs']} TeraMAC/s useful, {mfma_tf:.0f} TFLOP/s executed)")
+
+    gains = None
+    if args.gains_steps > 0:
+        gw, n_ent, fwd, adj = time_gains(torch, binding, synth, args.gains_steps, dev)
+        gains = {"workload": f"{gw.S} stations x 2 pol, {gw.SB} subbands x 64 channels, complex gains per input and channel",
+                 "forward_ms": round(fwd, 4), "adjoint_ms": round(adj, 4), "entries": n_ent,
+                 "forward_gbs": round(n_ent * 16 / (fwd * 1e-3) / 1e9, 1),
+                 "adjoint_gbs": round(n_ent * 16 / (adj * 1e-3) / 1e9, 1)}
+        log(f"bench: gains forward {fwd:.3f} ms, adjoint {adj:.3f} ms ({n_ent} visibility entries)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -484,6 +574,7 @@ def main():
         "plain_fp32_form": fp32,
         "coarse_delay_and_flags": flagged,
         "beamformer": beam,
+        "differentiable_gains": gains,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

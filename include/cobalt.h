@@ -196,10 +196,10 @@ int cobalt_channelize_ex(cobalt_plan* plan, const void* d_in, const double* h_de
  *   incoherent       per-station Stokes summed over stations,
  * with Stokes summed over n_int consecutive channel samples.  Requires an FP16-split plan
  * (the products run on matrix cores with hi/lo operands) and at most 56 stations.
- * Output layouts (float, time fastest):
- *   d_coherent    [SB][C][NB][n_stokes][N_c / n_int]
- *   d_voltages    [SB][C][NB][P][N_c] complex (re, im)
- *   d_incoherent  [SB][C][n_stokes][N_c / n_int]
+ * Output layouts (float, beams fastest: each output sample is one row over the beams):
+ *   d_coherent    [SB][C][N_c / n_int][n_stokes][NB]
+ *   d_voltages    [SB][C][N_c][P][NB] complex (re, im)
+ *   d_incoherent  [SB][C][N_c / n_int][n_stokes]
  * Any output may be NULL (not computed); at least one must be given. */
 typedef struct cobalt_beam_params {
     int32_t       n_beams;      /* NB >= 1                                                  */

@@ -337,8 +337,8 @@ class Plan:
     def beam_shapes(self, n_beams, n_stokes=4, n_int=1):
         """Shapes of the coherent Stokes, voltage and incoherent Stokes outputs."""
         n_out = self.n_c // n_int
-        return ((self.SB, self.C, n_beams, n_stokes, n_out), (self.SB, self.C, n_beams, 2, self.n_c, 2),
-                (self.SB, self.C, n_stokes, n_out))
+        return ((self.SB, self.C, n_out, n_stokes, n_beams), (self.SB, self.C, self.n_c, 2, n_beams, 2),
+                (self.SB, self.C, n_out, n_stokes))
 
     def _beam_call(self, fn, first, delays, dtau, n_stokes, n_int, coherent, voltages, incoherent, stream):
         t = self._torch

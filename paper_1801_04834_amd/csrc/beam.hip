@@ -38,17 +38,25 @@ __device__ __forceinline__ void split_h2(float a, float b, unsigned& hi, unsigne
     lo = __builtin_bit_cast(unsigned, l);
 }
 
-// LDS words per (plane, pol, sample) row: stations padded to 8k, plus 4 words so that rows of
-// consecutive samples start in different 16-byte bank groups
-template <int KS>
-constexpr int row_words() { return 8 * KS + 4; }
+// (a, b) -> (-b, a) on packed fp16 pairs: (Re w, -Im w) -> (Im w, Re w).  Exact for both the
+// hi and the lo part of the split (a sign flip and a move).
+__device__ __forceinline__ uintx4 re_to_im(uintx4 d) {
+    uintx4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = __builtin_amdgcn_alignbit(d[e], d[e], 16) ^ 0x00008000u;
+    return r;
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 template <int KS>
-__global__ __launch_bounds__(256, 1) void beam_kernel(BeamArgs a) {
-    constexpr int RW = row_words<KS>();
-    constexpr int kBuf = 2 * 2 * kBT * RW;              // words per staged block: [plane][pol][t][RW]
-    __shared__ __attribute__((aligned(16))) unsigned sm[2 * kBuf];   // double buffer
-    __shared__ float inc_part[8][4][kBT];               // incoherent partial sums [s-group][stokes][t]
+__global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
+    // one staged block = the channelised K block as stored: [plane][row][32 samples] words,
+    // rows padded to 16 KS (8 KS stations x 2 pols; padding rows stay zero)
+    constexpr int kRows = 16 * KS;
+    constexpr int kPlaneW = kRows * kBT;
+    constexpr int kBuf = 2 * kPlaneW;
+    __shared__ __attribute__((aligned(1024))) unsigned sm[2 * kBuf];   // double buffer
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t ch = blockIdx.x;                      // sb * C + c
@@ -59,7 +67,9 @@ __global__ __launch_bounds__(256, 1) void beam_kernel(BeamArgs a) {
 
     // ---- weights of this wave's beams: fp16 hi/lo fragments for every k-step ----
     const double f_c = a.f_sb[sb] + (double)(c - a.C / 2) * a.df;
-    uintx4 are_h[KS], are_l[KS], aim_h[KS], aim_l[KS];
+    // only the Re-part fragments are kept: the Im part (Im w, Re w) is (Re w, -Im w) with the
+    // halves swapped and the new low half negated, rebuilt per k-step in registers
+    uintx4 are_h[KS], are_l[KS];
     {
         const int b = bt * 32 + (lane & 31);
 #pragma unroll
@@ -74,71 +84,84 @@ __global__ __launch_bounds__(256, 1) void beam_kernel(BeamArgs a) {
                     wr = __builtin_amdgcn_cosf(r);
                     wi = __builtin_amdgcn_sinf(r);
                 }
-                unsigned h0, l0, h1, l1;
+                unsigned h0, l0;
                 split_h2(wr, -wi, h0, l0);
-                split_h2(wi, wr, h1, l1);
                 are_h[ks][u] = h0;
                 are_l[ks][u] = l0;
-                aim_h[ks][u] = h1;
-                aim_l[ks][u] = l1;
             }
         }
     }
 
-    // ---- staging: piece pc = (plane, row, 4-sample group) of 16 bytes; a block's pieces are
-    // loaded into registers before the previous block's products and written to LDS after
-    // them, so the loads overlap the MFMAs ----
+    // ---- staging: the block's rows go global -> LDS directly (global_load_lds, 16 bytes per
+    // lane, one instruction = 8 rows); the next block is requested before this block's
+    // products.  Fragments are then gathered per station row (4-byte reads). ----
     const int M = a.S * 2;
-    const int n_pieces = 2 * M * (kBT / 4);             // <= 256 KS, i.e. KS per thread
-    constexpr int kPieces = (2 * 2 * 8 * KS * (kBT / 4) + 255) / 256;
-    uint4 pre[kPieces];
-    auto load = [&](int kb) {
+    const int n_inst = (M + 7) / 8;                     // per plane
+    auto issue = [&](int kb, unsigned* buf) {
         const char* blk = chan + (int64_t)kb * (2 * M * 128);
-#pragma unroll
-        for (int i = 0; i < kPieces; ++i) {
-            const int pc = tid + 256 * i;
-            if (pc < n_pieces) {
-                const int pl = pc / (M * 8), rem = pc % (M * 8);
-                pre[i] = *(const uint4*)(blk + (int64_t)pl * (M * 128) + (rem >> 3) * 128 + (rem & 7) * 16);
-            }
+        for (int i = wv; i < 2 * n_inst; i += 4) {
+            const int pl = i / n_inst, j = i % n_inst;
+            const int row = 8 * j + (lane >> 3);
+            if (row < M)
+                __builtin_amdgcn_global_load_lds((const void*)(blk + (int64_t)pl * (M * 128) + row * 128 + (lane & 7) * 16),
+                                                 (lds_ptr_t)(buf + pl * kPlaneW + j * 256), 16, 0, 0);
         }
     };
-    auto store = [&](unsigned* buf) {
-#pragma unroll
-        for (int i = 0; i < kPieces; ++i) {
-            const int pc = tid + 256 * i;
-            if (pc < n_pieces) {
-                const int pl = pc / (M * 8), rem = pc % (M * 8), row = rem >> 3, g = rem & 7;
-                unsigned* dst = buf + ((pl * 2 + (row & 1)) * kBT + 4 * g) * RW + (row >> 1);
-                dst[0] = pre[i].x;
-                dst[RW] = pre[i].y;
-                dst[2 * RW] = pre[i].z;
-                dst[3 * RW] = pre[i].w;
-            }
-        }
-    };
-    // zero the station padding once in both buffers
-    for (int i = tid; i < 2 * 2 * 2 * kBT; i += 256) {
-        unsigned* r = sm + (i / (2 * 2 * kBT)) * kBuf + (i % (2 * 2 * kBT)) * RW;
-        for (int s = a.S; s < 8 * KS; ++s) r[s] = 0u;
+    // zero the padding rows M .. 16 KS of both planes of both buffers once
+    for (int i = tid; i < 2 * 2 * (kRows - M) * kBT; i += 256) {
+        const int bufi = i / (2 * (kRows - M) * kBT), rem = i % (2 * (kRows - M) * kBT);
+        const int pl = rem / ((kRows - M) * kBT), w = rem % ((kRows - M) * kBT);
+        sm[bufi * kBuf + pl * kPlaneW + M * kBT + w] = 0u;
     }
     const int n_kb = a.n_kb;
     const float vscale = a.vscale;
     const int nS = a.n_stokes;
     const int n_out = a.n_c / a.n_int;
+    const int g = a.n_int < kBT ? a.n_int : kBT;        // samples summed inside one block
+    const int hb = lane >> 5;
+    const int b = bt * 32 + (lane & 31);                // this lane's beam (output column)
+    const bool bvalid = b < a.NB;
+
+    // Stokes of one (beam, sample) from the two polarisations' voltages
+    auto stokes = [&](float xr, float xi, float yr, float yi, float* st) {
+        const float xx = xr * xr + xi * xi, yy = yr * yr + yi * yi;
+        st[0] = xx + yy;
+        st[1] = xx - yy;
+        st[2] = 2.f * (xr * yr + xi * yi);
+        st[3] = 2.f * (xi * yr - xr * yi);
+    };
+    // v of lane i plus v of lane i ^ 32
+    auto add_halves = [&](float v) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        return __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    };
+    // write or accumulate (windows longer than a block: blocks of one workgroup run in order)
+    auto put = [&](float* o, int tstart, float v) {
+        if (a.n_int <= kBT || tstart % a.n_int == 0) *o = v;
+        else *o += v;
+    };
+    // incoherent per-sample sums of a block, [buffer][sample][stokes], for windows > 8 samples
+    __shared__ float inc_t[2][kBT][4];
+    auto inc_finish = [&](int kbp) {                    // wave 0, after a barrier
+        if (wv != 0 || lane >= (kBT / g) * nS) return;
+        const int grp = lane / nS, k = lane % nS, tb0 = kbp * kBT + grp * g;
+        if (tb0 >= a.n_c) return;
+        float v = 0.f;
+        for (int u = 0; u < g; ++u) v += inc_t[kbp & 1][grp * g + u][k];
+        put((float*)a.incoherent + (ch * n_out + tb0 / a.n_int) * nS + k, tb0, v);
+    };
 
     __syncthreads();
-    if (n_kb > 0) {
-        load(0);
-        store(sm);
-    }
+    if (n_kb > 0) issue(0, sm);
     for (int kb = 0; kb < n_kb; ++kb) {
         unsigned* buf = sm + (kb & 1) * kBuf;
-        __syncthreads();                                // block kb is in LDS; buffer kb+1 is free
-        if (kb + 1 < n_kb) load(kb + 1);
-        const int t_lane = lane & 31, tb = kb * kBT;
+        __builtin_amdgcn_s_waitcnt(0);                  // this wave's transfers of block kb have landed
+        __syncthreads();                                // ... and everyone's; buffer kb+1 is free
+        if (do_inc && g > 8 && kb > 0) inc_finish(kb - 1);
+        if (kb + 1 < n_kb) issue(kb + 1, sm + ((kb + 1) & 1) * kBuf);
+        const int tb = kb * kBT;
 
-        // ---- coherent: 32 beams x 32 samples, both polarisations ----
+        // ---- coherent: D[t][b] = data (32 samples x K) . weights (K x 32 beams) ----
         if (bt * 32 < a.NB) {
             floatx16 re[2], im[2];
 #pragma unroll
@@ -148,107 +171,148 @@ __global__ __launch_bounds__(256, 1) void beam_kernel(BeamArgs a) {
             }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                half8 Bh[2], Bl[2];
+                half8 Dh[2], Dl[2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    const int off = (p * kBT + t_lane) * RW + 8 * ks + 4 * (lane >> 5);
-                    Bh[p] = __builtin_bit_cast(half8, *(const uintx4*)(buf + off));                 // plane 0 (hi)
-                    Bl[p] = __builtin_bit_cast(half8, *(const uintx4*)(buf + 2 * kBT * RW + off));  // plane 1 (lo)
+                    // stations 8 ks + 4 hb + u (u = 0..3), sample lane % 32: rows 2 s + p
+                    uintx4 h, l;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int w = (2 * (8 * ks + 4 * hb + u) + p) * kBT + (lane & 31);
+                        h[u] = buf[w];
+                        l[u] = buf[kPlaneW + w];
+                    }
+                    Dh[p] = __builtin_bit_cast(half8, h);
+                    Dl[p] = __builtin_bit_cast(half8, l);
                 }
-                const half8 Ah_re = __builtin_bit_cast(half8, are_h[ks]), Ah_im = __builtin_bit_cast(half8, aim_h[ks]);
-                const half8 Al_re = __builtin_bit_cast(half8, are_l[ks]), Al_im = __builtin_bit_cast(half8, aim_l[ks]);
+                const half8 Wh_re = __builtin_bit_cast(half8, are_h[ks]), Wh_im = __builtin_bit_cast(half8, re_to_im(are_h[ks]));
+                const half8 Wl_re = __builtin_bit_cast(half8, are_l[ks]), Wl_im = __builtin_bit_cast(half8, re_to_im(are_l[ks]));
                 // four independent accumulators between dependent products
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah_re, Bh[p], re[p], 0, 0, 0);
-                    im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah_im, Bh[p], im[p], 0, 0, 0);
+                    re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[p], Wh_re, re[p], 0, 0, 0);
+                    im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[p], Wh_im, im[p], 0, 0, 0);
                 }
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah_re, Bl[p], re[p], 0, 0, 0);
-                    im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah_im, Bl[p], im[p], 0, 0, 0);
+                    re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dl[p], Wh_re, re[p], 0, 0, 0);
+                    im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dl[p], Wh_im, im[p], 0, 0, 0);
                 }
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al_re, Bh[p], re[p], 0, 0, 0);
-                    im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al_im, Bh[p], im[p], 0, 0, 0);
+                    re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[p], Wl_re, re[p], 0, 0, 0);
+                    im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[p], Wl_im, im[p], 0, 0, 0);
+                }
+                // keep each k-step's fragments local (two workgroups per CU hide the LDS latency)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // register r of lane i holds sample t = 8 (r/4) + 4 (i/32) + r%4 of beam b
+            if (a.voltages && bvalid) {
+                float2* vo = (float2*)a.voltages;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int t = tb + 8 * (r >> 2) + 4 * hb + (r & 3);
+                    if (t < a.n_c) {
+                        const int64_t base = ((ch * a.n_c + t) * 2) * (int64_t)a.NB + b;
+                        vo[base] = make_float2(re[0][r] * vscale, im[0][r] * vscale);
+                        vo[base + a.NB] = make_float2(re[1][r] * vscale, im[1][r] * vscale);
+                    }
                 }
             }
-            const int t = tb + t_lane;
-            const bool tvalid = t < a.n_c;
+            if (a.coherent) {
+                // Stokes per register group q (samples 8q + 4 hb + u, u = 0..3), summed over g
+                // consecutive samples: runs of up to 4 sit in one lane's group; runs of 8 span
+                // the two lane halves; longer runs also span groups.  All register indices are
+                // compile-time; g and nS only select.
+                float* co = (float*)a.coherent;
+                const int per = g >= 8 ? g / 8 : 1;
+                float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int b = bt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const bool bvalid = b < a.NB;
-                const float xr = re[0][r] * vscale, xi = im[0][r] * vscale;
-                const float yr = re[1][r] * vscale, yi = im[1][r] * vscale;
-                if (a.voltages && bvalid && tvalid) {
-                    float2* vo = (float2*)a.voltages + ((ch * a.NB + b) * 2) * (int64_t)a.n_c;
-                    vo[t] = make_float2(xr, xi);
-                    vo[a.n_c + t] = make_float2(yr, yi);
-                }
-                if (a.coherent) {
-                    // Stokes of this (beam, sample); samples past N_c contribute zero
-                    const float xx = xr * xr + xi * xi, yy = yr * yr + yi * yi;
-                    float st4[4] = {xx + yy, xx - yy, 2.f * (xr * yr + xi * yi), 2.f * (xi * yr - xr * yi)};
+                for (int q = 0; q < 4; ++q) {
+                    float st[4][4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        if (k >= nS) break;
-                        float v = tvalid ? st4[k] : 0.f;
-                        const int ni = a.n_int < kBT ? a.n_int : kBT;
-                        for (int m = 1; m < ni; m <<= 1) v += __shfl_xor(v, m, 64);    // within 32-lane halves
-                        if (bvalid && (t_lane % ni) == 0 && tvalid) {
-                            float* so = (float*)a.coherent + ((ch * a.NB + b) * nS + k) * (int64_t)n_out;
-                            const int to = t / a.n_int;
-                            if (a.n_int <= kBT || (t % a.n_int) == 0) so[to] = v;
-                            else so[to] += v;                   // same workgroup, blocks in order
+                    for (int u = 0; u < 4; ++u) {
+                        const int r = 4 * q + u;
+                        stokes(re[0][r] * vscale, im[0][r] * vscale, re[1][r] * vscale, im[1][r] * vscale, st[u]);
+                        if (tb + 8 * q + 4 * hb + u >= a.n_c)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) st[u][k] = 0.f;
+                    }
+                    if (g <= 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int t = tb + 8 * q + 4 * hb + u;
+                            const bool lead = (u & (g - 1)) == 0;
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                if (k >= nS) break;
+                                float v = st[u][k];
+#pragma unroll
+                                for (int w = 1; w < 4; ++w)
+                                    if (u + w < 4 && w < g) v += st[u + w][k];
+                                if (lead && bvalid && t < a.n_c)
+                                    co[((ch * n_out + t / a.n_int) * nS + k) * (int64_t)a.NB + b] = v;
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            part[k] += st[0][k] + st[1][k] + st[2][k] + st[3][k];
+                        if ((q + 1) % per == 0) {              // window of g samples complete
+                            const int t = tb + 8 * (q + 1 - per);
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                if (k >= nS) break;
+                                const float v = add_halves(part[k]);
+                                if (hb == 0 && bvalid && t < a.n_c)
+                                    put(co + ((ch * n_out + t / a.n_int) * nS + k) * (int64_t)a.NB + b, t, v);
+                            }
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) part[k] = 0.f;
                         }
                     }
                 }
             }
         }
 
-        // ---- incoherent: sum over stations of per-station Stokes (one workgroup per channel) ----
+        // ---- incoherent: wave w sums samples 8w .. 8w+7; lane = (station group, sample) ----
         if (do_inc) {
-            const int t = tid & 31, grp = tid >> 5;         // 8 groups of stations
+            const int tl = 8 * wv + (lane & 7), grp = lane >> 3;
             float acc[4] = {0.f, 0.f, 0.f, 0.f};
             for (int s = grp; s < a.S; s += 8) {
-                float x[2], y[2];
+                float v[2][2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    const unsigned hw = buf[(p * kBT + t) * RW + s], lw = buf[(2 * kBT + p * kBT + t) * RW + s];
+                    const unsigned hw = buf[(2 * s + p) * kBT + tl], lw = buf[kPlaneW + (2 * s + p) * kBT + tl];
                     const half2v h = __builtin_bit_cast(half2v, hw), l = __builtin_bit_cast(half2v, lw);
-                    const float vr = ((float)h.x + (float)l.x) * vscale, vi = ((float)h.y + (float)l.y) * vscale;
-                    if (p == 0) { x[0] = vr; x[1] = vi; } else { y[0] = vr; y[1] = vi; }
+                    v[p][0] = ((float)h.x + (float)l.x) * vscale;
+                    v[p][1] = ((float)h.y + (float)l.y) * vscale;
                 }
-                const float xx = x[0] * x[0] + x[1] * x[1], yy = y[0] * y[0] + y[1] * y[1];
-                acc[0] += xx + yy;
-                acc[1] += xx - yy;
-                acc[2] += 2.f * (x[0] * y[0] + x[1] * y[1]);
-                acc[3] += 2.f * (x[1] * y[0] - x[0] * y[1]);
+                float st4[4];
+                stokes(v[0][0], v[0][1], v[1][0], v[1][1], st4);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] += st4[k];
             }
+            const int t = tb + tl;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) inc_part[grp][k][t] = acc[k];
-            __syncthreads();
-            if (tid < 32 * nS) {
-                const int k = tid >> 5, tt = tid & 31;
-                float v = 0.f;
-#pragma unroll
-                for (int g2 = 0; g2 < 8; ++g2) v += inc_part[g2][k][tt];
-                const int tg = tb + tt;
-                if (tg >= a.n_c) v = 0.f;
-                const int ni = a.n_int < kBT ? a.n_int : kBT;
-                for (int m = 1; m < ni; m <<= 1) v += __shfl_xor(v, m, 64);
-                if ((tt % ni) == 0 && tg < a.n_c) {
-                    float* so = (float*)a.incoherent + (ch * nS + k) * (int64_t)n_out;
-                    const int to = tg / a.n_int;
-                    if (a.n_int <= kBT || (tg % a.n_int) == 0) so[to] = v;
-                    else so[to] += v;
+            for (int k = 0; k < 4; ++k) {
+                float x = t < a.n_c ? acc[k] : 0.f;
+                x += __shfl_xor(x, 8, 64);
+                x += __shfl_xor(x, 16, 64);
+                x += __shfl_xor(x, 32, 64);              // every lane: the sum over station groups
+                if (g <= 8) {
+                    for (int m = 1; m < g; m <<= 1) x += __shfl_xor(x, m, 64);
+                    if (k < nS && grp == 0 && (tl % g) == 0 && t < a.n_c)
+                        ((float*)a.incoherent)[(ch * n_out + t / a.n_int) * nS + k] = x;
+                } else if (grp == 0) {
+                    inc_t[kb & 1][tl][k] = x;
                 }
             }
-            __syncthreads();                                // inc_part reused next block
         }
-        if (kb + 1 < n_kb) store(sm + ((kb + 1) & 1) * kBuf);
+    }
+    if (do_inc && g > 8 && n_kb > 0) {
+        __syncthreads();
+        inc_finish(n_kb - 1);
     }
 }
 

@@ -65,9 +65,9 @@ struct BeamArgs {
     int64_t chan_stride;     // bytes per channel
     const double* f_sb;      // [SB] subband sky centre frequency (Hz)
     const double* dtau;      // [NB][S] beam delay offsets (s), device
-    void* coherent;          // [SB*C][NB][n_stokes][N_c/n_int] float, or null
-    void* voltages;          // [SB*C][NB][P][N_c] float (re, im), or null
-    void* incoherent;        // [SB*C][n_stokes][N_c/n_int] float, or null
+    void* coherent;          // [SB*C][N_c/n_int][n_stokes][NB] float, or null
+    void* voltages;          // [SB*C][N_c][P][NB] float (re, im), or null
+    void* incoherent;        // [SB*C][N_c/n_int][n_stokes] float, or null
     double df;               // channel width (Hz)
     int32_t C, S, NB, n_c, n_kb, n_chan, n_int, n_stokes;
     float vscale;            // 2^-k: undoes the FP16-split prescale

@@ -43,6 +43,10 @@ def _oracle(w, blocks, dtau, n_stokes, n_int):
 
 
 def _check(label, coh, volt, inc, o):
+    """GPU outputs are beam-fastest; the oracle's are time-fastest."""
+    coh = coh.transpose(0, 1, 4, 3, 2)
+    volt = volt.transpose(0, 1, 4, 3, 2, 5)
+    inc = inc.transpose(0, 1, 3, 2)
     B = o["beams"]
     Vg = volt[..., 0].astype(np.float64) + 1j * volt[..., 1]
     rms = np.sqrt(np.mean(np.abs(B) ** 2))
@@ -116,7 +120,7 @@ def test_pointed_beam_on_a_tone():
             plan.beamform(xb, np.zeros((S, 2)), dt, 4, n_c, coherent=coh, incoherent=inc)
         torch.cuda.synchronize()
         one = n_c * (A * float(np.sum(w.fir().astype(np.float64)))) ** 2
-        I = coh.cpu().numpy()[0, c0, :, 0, 0]
+        I = coh.cpu().numpy()[0, c0, 0, 0, :]
         _say(f"  pointed {I[0] / (2 * S * S * one):.6f}  centre {I[1] / (2 * S * S * one):.4f}")
         assert abs(I[0] - 2 * S * S * one) <= 2e-5 * I[0]
         assert I[1] < 0.6 * I[0]
