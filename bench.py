@@ -527,8 +527,8 @@ def main():
                 "real_time_factor": round(bw.N / synth.SAMPLE_RATE_HZ / ((float(np.mean(bf_ms)) + b_ms) * 1e-3), 2),
                 "roofline": {"bound": "mfma", "achieved": round(mfma_tf, 1), "peak": FP16_MFMA_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4),
-                             "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}>"),
-                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}>"}}
+                             "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}, 1>"),
+                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1>"}}
         log(f"bench: beamformer F {np.mean(bf_ms):.3f} ms + beams {b_ms:.3f} ms "
             f"({beam['beam_tcmacs']} TeraMAC/s useful, {mfma_tf:.0f} TFLOP/s executed)")
 

@@ -49,7 +49,7 @@ __device__ __forceinline__ uintx4 re_to_im(uintx4 d) {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-template <int KS>
+template <int KS, int NS>
 __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
     // one staged block = the channelised K block as stored: [plane][row][32 samples] words,
     // rows padded to 16 KS (8 KS stations x 2 pols; padding rows stay zero)
@@ -115,20 +115,31 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
     }
     const int n_kb = a.n_kb;
     const float vscale = a.vscale;
-    const int nS = a.n_stokes;
+    constexpr int nS = NS;                              // Stokes parameters: 1 (I) or 4 (IQUV)
+    const float sscale = vscale * vscale;               // Stokes are quadratic in the voltages
     const int n_out = a.n_c / a.n_int;
     const int g = a.n_int < kBT ? a.n_int : kBT;        // samples summed inside one block
+    const int gsh = __builtin_ctz((unsigned)g);         // g is a power of two
+    // output index of a window starting at sample t: t / n_int (a shift for n_int <= 32)
+    auto out_index = [&](int t) { return a.n_int <= kBT ? (t >> gsh) : t / a.n_int; };
+    // per-channel output bases (32-bit offsets below)
+    float* const co_ch = a.coherent ? (float*)a.coherent + ch * (int64_t)n_out * nS * a.NB : nullptr;
+    float2* const vo_ch = a.voltages ? (float2*)a.voltages + ch * (int64_t)a.n_c * 2 * a.NB : nullptr;
+    float* const io_ch = a.incoherent ? (float*)a.incoherent + ch * (int64_t)n_out * nS : nullptr;
     const int hb = lane >> 5;
     const int b = bt * 32 + (lane & 31);                // this lane's beam (output column)
     const bool bvalid = b < a.NB;
 
     // Stokes of one (beam, sample) from the two polarisations' voltages
+    // Stokes of one (beam, sample) from the two polarisations' voltages (unscaled)
     auto stokes = [&](float xr, float xi, float yr, float yi, float* st) {
         const float xx = xr * xr + xi * xi, yy = yr * yr + yi * yi;
         st[0] = xx + yy;
-        st[1] = xx - yy;
-        st[2] = 2.f * (xr * yr + xi * yi);
-        st[3] = 2.f * (xi * yr - xr * yi);
+        if constexpr (NS == 4) {
+            st[1] = xx - yy;
+            st[2] = 2.f * (xr * yr + xi * yi);
+            st[3] = 2.f * (xi * yr - xr * yi);
+        }
     };
     // v of lane i plus v of lane i ^ 32
     auto add_halves = [&](float v) {
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
         if (tb0 >= a.n_c) return;
         float v = 0.f;
         for (int u = 0; u < g; ++u) v += inc_t[kbp & 1][grp * g + u][k];
-        put((float*)a.incoherent + (ch * n_out + tb0 / a.n_int) * nS + k, tb0, v);
+        put(io_ch + out_index(tb0) * nS + k, tb0, v);
     };
 
     __syncthreads();
@@ -208,14 +219,13 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
             }
             // register r of lane i holds sample t = 8 (r/4) + 4 (i/32) + r%4 of beam b
             if (a.voltages && bvalid) {
-                float2* vo = (float2*)a.voltages;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int t = tb + 8 * (r >> 2) + 4 * hb + (r & 3);
                     if (t < a.n_c) {
-                        const int64_t base = ((ch * a.n_c + t) * 2) * (int64_t)a.NB + b;
-                        vo[base] = make_float2(re[0][r] * vscale, im[0][r] * vscale);
-                        vo[base + a.NB] = make_float2(re[1][r] * vscale, im[1][r] * vscale);
+                        const unsigned o = (unsigned)(t * 2 * a.NB + b);
+                        vo_ch[o] = make_float2(re[0][r] * vscale, im[0][r] * vscale);
+                        vo_ch[o + a.NB] = make_float2(re[1][r] * vscale, im[1][r] * vscale);
                     }
                 }
             }
@@ -224,19 +234,18 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                 // consecutive samples: runs of up to 4 sit in one lane's group; runs of 8 span
                 // the two lane halves; longer runs also span groups.  All register indices are
                 // compile-time; g and nS only select.
-                float* co = (float*)a.coherent;
                 const int per = g >= 8 ? g / 8 : 1;
-                float part[4] = {0.f, 0.f, 0.f, 0.f};
+                float part[NS] = {};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    float st[4][4];
+                    float st[4][NS];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int r = 4 * q + u;
-                        stokes(re[0][r] * vscale, im[0][r] * vscale, re[1][r] * vscale, im[1][r] * vscale, st[u]);
+                        stokes(re[0][r], im[0][r], re[1][r], im[1][r], st[u]);
                         if (tb + 8 * q + 4 * hb + u >= a.n_c)
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) st[u][k] = 0.f;
+                            for (int k = 0; k < NS; ++k) st[u][k] = 0.f;
                     }
                     if (g <= 4) {
 #pragma unroll
@@ -244,31 +253,29 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                             const int t = tb + 8 * q + 4 * hb + u;
                             const bool lead = (u & (g - 1)) == 0;
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                if (k >= nS) break;
+                            for (int k = 0; k < NS; ++k) {
                                 float v = st[u][k];
 #pragma unroll
                                 for (int w = 1; w < 4; ++w)
                                     if (u + w < 4 && w < g) v += st[u + w][k];
                                 if (lead && bvalid && t < a.n_c)
-                                    co[((ch * n_out + t / a.n_int) * nS + k) * (int64_t)a.NB + b] = v;
+                                    co_ch[(unsigned)((out_index(t) * nS + k) * a.NB + b)] = v * sscale;
                             }
                         }
                     } else {
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
+                        for (int k = 0; k < NS; ++k)
                             part[k] += st[0][k] + st[1][k] + st[2][k] + st[3][k];
                         if ((q + 1) % per == 0) {              // window of g samples complete
                             const int t = tb + 8 * (q + 1 - per);
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                if (k >= nS) break;
-                                const float v = add_halves(part[k]);
+                            for (int k = 0; k < NS; ++k) {
+                                const float v = add_halves(part[k]) * sscale;
                                 if (hb == 0 && bvalid && t < a.n_c)
-                                    put(co + ((ch * n_out + t / a.n_int) * nS + k) * (int64_t)a.NB + b, t, v);
+                                    put(co_ch + (unsigned)((out_index(t) * nS + k) * a.NB + b), t, v);
                             }
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) part[k] = 0.f;
+                            for (int k = 0; k < NS; ++k) part[k] = 0.f;
                         }
                     }
                 }
@@ -278,32 +285,32 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
         // ---- incoherent: wave w sums samples 8w .. 8w+7; lane = (station group, sample) ----
         if (do_inc) {
             const int tl = 8 * wv + (lane & 7), grp = lane >> 3;
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+            float acc[NS] = {};
             for (int s = grp; s < a.S; s += 8) {
                 float v[2][2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const unsigned hw = buf[(2 * s + p) * kBT + tl], lw = buf[kPlaneW + (2 * s + p) * kBT + tl];
-                    const half2v h = __builtin_bit_cast(half2v, hw), l = __builtin_bit_cast(half2v, lw);
-                    v[p][0] = ((float)h.x + (float)l.x) * vscale;
-                    v[p][1] = ((float)h.y + (float)l.y) * vscale;
+                    // hi + lo of the (re, im) halves in one mixed-precision FMA each (exact in FP32)
+                    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(v[p][0]) : "v"(hw), "v"(lw));
+                    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(v[p][1]) : "v"(hw), "v"(lw));
                 }
-                float st4[4];
+                float st4[NS];
                 stokes(v[0][0], v[0][1], v[1][0], v[1][1], st4);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] += st4[k];
+                for (int k = 0; k < NS; ++k) acc[k] += st4[k];
             }
             const int t = tb + tl;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float x = t < a.n_c ? acc[k] : 0.f;
+            for (int k = 0; k < NS; ++k) {
+                float x = t < a.n_c ? acc[k] * sscale : 0.f;
                 x += __shfl_xor(x, 8, 64);
                 x += __shfl_xor(x, 16, 64);
                 x += __shfl_xor(x, 32, 64);              // every lane: the sum over station groups
                 if (g <= 8) {
                     for (int m = 1; m < g; m <<= 1) x += __shfl_xor(x, m, 64);
-                    if (k < nS && grp == 0 && (tl % g) == 0 && t < a.n_c)
-                        ((float*)a.incoherent)[(ch * n_out + t / a.n_int) * nS + k] = x;
+                    if (grp == 0 && (tl % g) == 0 && t < a.n_c)
+                        io_ch[out_index(t) * nS + k] = x;
                 } else if (grp == 0) {
                     inc_t[kb & 1][tl][k] = x;
                 }
@@ -319,7 +326,10 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
 template <int KS>
 hipError_t launch_ks(const BeamArgs& a, hipStream_t st) {
     const dim3 grid((unsigned)a.n_chan, (unsigned)((a.NB + 127) / 128)), block(256);
-    hipLaunchKernelGGL((beam_kernel<KS>), grid, block, 0, st, a);
+    if (a.n_stokes == 1)
+        hipLaunchKernelGGL((beam_kernel<KS, 1>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((beam_kernel<KS, 4>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 

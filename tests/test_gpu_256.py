@@ -111,3 +111,22 @@ def test_256_channel_tone_lands_in_its_channel():
     auto = V[:, 0, 0].real
     assert int(np.argmax(auto)) == c0
     assert abs(auto[c0] - want) <= 1e-4 * want
+
+
+def test_256_channel_plan_rejects_lost_sample_flags():
+    """The flag path is built for 64 channels; a 256-channel plan refuses flags but still
+    takes coarse offsets and weights (all N_c without flags)."""
+    from paper_1801_04834_amd import binding
+    w = _work(2, 1, 40, synth.CI16, synth.X_FP16_SPLIT, 2590)
+    _say("CASE c256 flags rejected")
+    with binding.plan_for(w) as plan:
+        G = 3
+        x = torch.from_numpy(synth.guarded_rows(w, 0, G)).cuda()
+        fl = torch.zeros((w.S, w.SB, plan.flag_words(w.N + G)), dtype=torch.int32, device="cuda")
+        with pytest.raises(binding.CobaltError) as ei:
+            plan.correlate_ex(x, w.delays(0), flags=fl)
+        assert ei.value.code == binding.EUNSUPPORTED
+        wts = torch.zeros(plan.weights_shape(), dtype=torch.int32, device="cuda")
+        plan.correlate_ex(x, w.delays(0), coarse=np.array([0, G], np.int32), weights=wts)
+        torch.cuda.synchronize()
+        assert (wts.cpu().numpy() == 40).all()
