@@ -450,7 +450,7 @@ def main():
         wall_p = time_pipelined(torch, plan, x, delays, args.steps, args.warmup)
         log(f"bench: pipelined (F of block k+1 overlapping X of block k) {wall_p * 1e3:.3f} ms/step")
         step_ms = wall_p * 1e3
-    lat = block_latency(torch, plan, x, delays, max(args.steps, 20))
+    lat = block_latency(torch, plan, x, delays, max(args.steps, 60))
     log(f"bench: block latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
     # algorithmic work per launch
