@@ -13,7 +13,10 @@
 // and the k order inside a fragment never matters.  A' is built in registers from the
 // B-role fragments.
 //   FP16-split: Z*2^k = hi + lo (two fp16 planes); V ~= hh + hl + lh accumulated in FP32
-//   (the dropped lo*lo term is below 2^-22 of |Z|^2), scaled back by 2^-2k.
+//   (the dropped lo*lo term is below 2^-22 of |Z|^2), scaled back by 2^-2k.  On a diagonal
+//   tile (I = J) the lh product is the transpose of hl (real part) and minus its transpose
+//   (imaginary part), so it is not multiplied but added from hl at the end (where registers
+//   allow: every diagonal tile of the 152-input grid).
 //   int8: exact int32 sums.
 // Plain FP32 form: 8x8 register blocks of complex FMAs on the VALU.
 #include <type_traits>
@@ -58,6 +61,17 @@ constexpr unsigned wave_blocks(int R, int W, bool as_b) {
     for (int t = kTilesPerWave * W; t < kTilesPerWave * W + kTilesPerWave && t < tile_count(R); ++t)
         m |= 1u << (as_b ? tile_J(R, t) : tile_I(R, t));
     return m;
+}
+
+// Whether wave W of an R-block grid forms lh of its diagonal tiles from hl (FP16-split): each
+// such tile holds one more accumulator pair, so only where at most 5 pairs fit in registers.
+constexpr bool diag_from_hl(int R, int W) {
+    int n = 0, d = 0;
+    for (int t = kTilesPerWave * W; t < kTilesPerWave * W + kTilesPerWave && t < tile_count(R); ++t) {
+        ++n;
+        if (tile_I(R, t) == tile_J(R, t)) ++d;
+    }
+    return n + d <= 5;
 }
 
 template <int MODE> struct XCfg;
@@ -156,14 +170,18 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
     constexpr int NW = NT - T0 <= 0 ? 0 : (NT - T0 > kTilesPerWave ? kTilesPerWave : NT - T0);
     constexpr unsigned useA = wave_blocks(R, W, false) | wave_blocks(R, W, true);
     constexpr unsigned useB = wave_blocks(R, W, true);
+    constexpr bool kDiagHl = MODE == XM_FP16_SPLIT && diag_from_hl(R, W);
     constexpr int kBufB = R * 32 * kRowB;
     const int lane = tid & 63;
 
     acc_t vre[kTilesPerWave], vim[kTilesPerWave];
+    acc_t xre[kTilesPerWave], xim[kTilesPerWave];     // hl of diagonal tiles (FP16-split)
 #pragma unroll
     for (int t = 0; t < kTilesPerWave; ++t) {
         vre[t] = acc_t{};
         vim[t] = acc_t{};
+        xre[t] = acc_t{};
+        xim[t] = acc_t{};
     }
 
     // rows M .. 32R-1 stay zero in both buffers
@@ -202,18 +220,26 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
                             gl[b] = swapneg_f16(fl[b]);
                         }
                     });
-                    // three products, each over all tiles: independent accumulators between
-                    // dependent MFMAs
+                    // three products (hh, hl, lh), each over all tiles: independent accumulators
+                    // between dependent MFMAs; diagonal tiles keep hl apart and skip lh
                     static_for<3>([&](auto pi) {
                         constexpr int pr = decltype(pi)::value;
                         static_for<NW>([&](auto ti) {
                             constexpr int t = decltype(ti)::value;
                             constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
-                            const frag_t A = __builtin_bit_cast(frag_t, pr == 2 ? fl[I] : fh[I]);
-                            const frag_t B = __builtin_bit_cast(frag_t, pr == 1 ? fl[J] : fh[J]);
-                            const frag_t Bs = __builtin_bit_cast(frag_t, pr == 1 ? gl[J] : gh[J]);
-                            vre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, vre[t], 0, 0, 0);
-                            vim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Bs, vim[t], 0, 0, 0);
+                            constexpr bool dg = kDiagHl && I == J;
+                            if constexpr (!(dg && pr == 2)) {
+                                const frag_t A = __builtin_bit_cast(frag_t, pr == 2 ? fl[I] : fh[I]);
+                                const frag_t B = __builtin_bit_cast(frag_t, pr == 1 ? fl[J] : fh[J]);
+                                const frag_t Bs = __builtin_bit_cast(frag_t, pr == 1 ? gl[J] : gh[J]);
+                                if constexpr (dg && pr == 1) {
+                                    xre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, xre[t], 0, 0, 0);
+                                    xim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Bs, xim[t], 0, 0, 0);
+                                } else {
+                                    vre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, vre[t], 0, 0, 0);
+                                    vim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Bs, vim[t], 0, 0, 0);
+                                }
+                            }
                         });
                     });
                 } else {
@@ -236,6 +262,34 @@ __device__ __forceinline__ void xwave(const XArgs& a, const char* __restrict__ c
             }
         }
         cur ^= 1;
+    }
+
+    // ---- diagonal tiles (FP16-split): Re += hl + hl^T, Im += hl - hl^T, through LDS ----
+    if constexpr (MODE == XM_FP16_SPLIT) {
+        __syncthreads();                      // every wave is done with the chunk buffers
+        constexpr int kTw = 2 * 32 * 33;      // floats per wave: two padded 32 x 32 tiles
+        float* tr = (float*)lds + W * kTw;
+        static_for<NW>([&](auto ti) {
+            constexpr int t = decltype(ti)::value;
+            constexpr int I = tile_I(R, T0 + t), J = tile_J(R, T0 + t);
+            if constexpr (kDiagHl && I == J) {
+                static_assert((W + 1) * kTw * 4 <= 2 * R * 32 * kRowB, "transpose area inside LDS");
+                const int col = lane & 31;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    tr[row * 33 + col] = xre[t][r];
+                    tr[32 * 33 + row * 33 + col] = xim[t][r];
+                }
+                // the same wave reads the transpose back (its LDS operations complete in order)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    vre[t][r] += xre[t][r] + tr[col * 33 + row];
+                    vim[t][r] += xim[t][r] - tr[32 * 33 + col * 33 + row];
+                }
+            }
+        });
     }
 
     // ---- epilogue: stored baselines s1 >= s2, all four polarisation products ----
