@@ -139,13 +139,16 @@ template <int ST, int C>
 struct PassBuf {
     using raw_t = typename Samp<ST>::raw_t;
     raw_t v[kPass];
-    __device__ __forceinline__ void load(const raw_t* __restrict__ in, uint32_t ulane, int jb, int n_c) {
+    // rows jb .. jb + 31 of this wave's phases: a wave-uniform base for the pass and per-lane
+    // offsets lane + r*C, so the loads take a scalar base, one offset register and immediates
+    __device__ __forceinline__ void load(const raw_t* __restrict__ in, int lane, int jb, int n_c) {
+        const raw_t* __restrict__ rows = in + (int64_t)jb * C;
         if (jb + kPass <= n_c) {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r] = in[(uint32_t)((jb + r) * C) + ulane];
+            for (int r = 0; r < kPass; ++r) v[r] = rows[r * C + lane];
         } else {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r] = jb + r < n_c ? in[(uint32_t)((jb + r) * C) + ulane] : raw_t{};
+            for (int r = 0; r < kPass; ++r) v[r] = jb + r < n_c ? rows[r * C + lane] : raw_t{};
         }
     }
     __device__ __forceinline__ raw_t get(int r) const { return v[r]; }
@@ -154,13 +157,14 @@ typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
 template <int C>
 struct PassBuf<ST_CI8, C> {
     ushort2v v[kPass / 2];
-    __device__ __forceinline__ void load(const uint16_t* __restrict__ in, uint32_t ulane, int jb, int n_c) {
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ in, int lane, int jb, int n_c) {
+        const uint16_t* __restrict__ rows = in + (int64_t)jb * C;
         if (jb + kPass <= n_c) {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = in[(uint32_t)((jb + r) * C) + ulane];
+            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = rows[r * C + lane];
         } else {
 #pragma unroll
-            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = jb + r < n_c ? in[(uint32_t)((jb + r) * C) + ulane] : (uint16_t)0;
+            for (int r = 0; r < kPass; ++r) v[r / 2][r % 2] = jb + r < n_c ? rows[r * C + lane] : (uint16_t)0;
         }
     }
     __device__ __forceinline__ uint16_t get(int r) const { return v[r / 2][r % 2]; }
@@ -284,10 +288,10 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
     // samples; float samples, 2 VGPRs each, are loaded at the top of the pass instead).
     constexpr bool kPrefetch = ST != ST_CF32;
     PassBuf<ST, C> nw;
-    if constexpr (kPrefetch) nw.load(inw, ulane, j0, a.n_c);
+    if constexpr (kPrefetch) nw.load(inw, lane, j0, a.n_c);
 
     for (int jb = j0; jb < jend; jb += kPass) {
-        if constexpr (!kPrefetch) nw.load(inw, ulane, jb, a.n_c);
+        if constexpr (!kPrefetch) nw.load(inw, lane, jb, a.n_c);
 
         // ---- polyphase FIR: y_j[p] = sum_t h[t*C + p] x[(j - T + 1 + t)*C + p] ----
         // input-stationary: window row w feeds outputs j = w - t (taps in ascending t)
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
 #pragma unroll
         for (int i = 0; i < kHistRows; ++i) tail[i] = nw.get(kPass - kHistRows + i);
         if constexpr (kPrefetch) {
-            if (jb + kPass < jend) nw.load(inw, ulane, jb + kPass, a.n_c);
+            if (jb + kPass < jend) nw.load(inw, lane, jb + kPass, a.n_c);
         }
 
         // Channel samples past N_c and flagged ones (their FIR window reads a lost sample) are
