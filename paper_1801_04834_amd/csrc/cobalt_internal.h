@@ -9,7 +9,6 @@ namespace cobalt {
 
 // Built instantiations: C = 64 channels (the correlator setting) and C = 256 (the paper's
 // beamformer front end and the correlator's finest resolution), T = 16 taps.
-constexpr int kC = 64;                         // channels of the flag path (one row = two flag words)
 constexpr int kT = 16;
 constexpr int kHistRows = kT - 1;              // FIR history in rows of C samples
 constexpr int kKBlock = 32;                    // channel samples per K block of the channelised layout
@@ -26,8 +25,8 @@ struct FArgs {
     const void* hist_old;    // [S*P*SB][kHistRows*C] samples, stream order (s*P + p)*SB + sb
     void* hist_new;          // same layout, written by the last chunk of each stream
     void* out;               // channelised buffer, K-blocked (see cobalt.h)
-    const float* fir;        // [kT * kC]
-    const float* bscale;     // [kC] bandpass * mode scale (2^k or requant gain)
+    const float* fir;        // [kT * C]
+    const float* bscale;     // [C] bandpass * mode scale (2^k or requant gain)
     const double* f_sb;      // [SB] subband sky centre frequency (Hz)
     const double* delays;    // [S][2] residual delay (s) at block start / end
     const int32_t* coarse;   // [S] window start of each station in its rows, or null (0)
@@ -49,6 +48,7 @@ struct FlagArgs {
     uint32_t* hist_new;      // same, for the next block
     uint32_t* cflag;         // [S*SB][n_words]
     int32_t S, SB, n_c, n_words;
+    int32_t C;               // samples per row (channels): a multiple of 32
 };
 
 struct XArgs {

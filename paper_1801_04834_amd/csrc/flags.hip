@@ -17,7 +17,6 @@
 namespace cobalt {
 namespace {
 
-static_assert(kC == 64, "a row of C samples spans two flag words");
 static_assert(kHistRows == 15, "history bits 17..31 of the previous row word");
 
 // One wave per (station, subband): lanes take 64 consecutive row words at a time; the
@@ -34,19 +33,21 @@ __global__ __launch_bounds__(64) void chanflag_kernel(FlagArgs a) {
     uint32_t carry = a.hist_old[sst];
     uint32_t* __restrict__ out = a.cflag + sst * a.n_words;
     const int wl = (a.n_c - 1) >> 5;                       // row word holding the last row
+    const int wr = a.C >> 5;                               // flag words per row of C samples
     for (int w0 = 0; w0 < a.n_words; w0 += 64) {
         const int w = w0 + lane;
         uint32_t rw = 0;
         if (fl && w < a.n_words) {
-            // rows r = 32w + i cover samples g + 64r .. g + 64r + 63 of the row: bits b..31 of
-            // word i0, all of word i0+1 and bits 0..b-1 of word i0+2 (present when b > 0,
-            // since the window ends inside the row)
+            // rows r = 32w + i cover samples g + Cr .. g + Cr + C-1 of the row: bits b..31 of
+            // word i0, all of words i0+1 .. i0+C/32-1 and bits 0..b-1 of word i0+C/32 (present
+            // when b > 0, since the window ends inside the row)
             const int rmax = min(32, a.n_c - 32 * w);
-            const int64_t base = (g >> 5) + (int64_t)w * 64;
+            const int64_t base = (g >> 5) + (int64_t)w * 32 * wr;
             for (int i = 0; i < rmax; ++i) {
-                const int64_t i0 = base + 2 * i;
-                uint32_t any = (fl[i0] >> b) | fl[i0 + 1];
-                if (b) any |= fl[i0 + 2] & lowmask;
+                const int64_t i0 = base + (int64_t)wr * i;
+                uint32_t any = fl[i0] >> b;
+                for (int k = 1; k < wr; ++k) any |= fl[i0 + k];
+                if (b) any |= fl[i0 + wr] & lowmask;
                 rw |= (any != 0u ? 1u : 0u) << i;
             }
         }

@@ -252,6 +252,7 @@ int run_flags(cobalt_plan* p, const uint32_t* d_flags, int64_t row_len, const in
     a.SB = (int)z.SB;
     a.n_c = (int)z.n_c;
     a.n_words = (int)z.n_words;
+    a.C = (int)z.C;
     hipError_t e = launch_chanflags(a, st);
     if (e != hipSuccess) return hip_fail(e, "flag launch");
     p->rowhist_cur ^= 1;
@@ -437,7 +438,6 @@ static int do_fx(cobalt_plan* p, const void* d_in, const double* h_delays, const
         h_coarse = ext->h_coarse_offset;
         d_flags = ext->d_flags;
         d_weights = ext->d_weights;
-        if (d_flags && z.C != kC) return fail(COBALT_EUNSUPPORTED, "lost-sample flags are built for %d channels only", kC);
         if (((uintptr_t)d_flags | (uintptr_t)d_weights) % 4)
             return fail(COBALT_EINVAL, "d_flags and d_weights must be 4-byte aligned");
     }

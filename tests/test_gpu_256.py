@@ -113,20 +113,25 @@ def test_256_channel_tone_lands_in_its_channel():
     assert abs(auto[c0] - want) <= 1e-4 * want
 
 
-def test_256_channel_plan_rejects_lost_sample_flags():
-    """The flag path is built for 64 channels; a 256-channel plan refuses flags but still
-    takes coarse offsets and weights (all N_c without flags)."""
+def test_256_channel_flags_drop_whole_fir_windows():
+    """One lost sample of station 0 at 256 channels: exactly the T = 16 channel samples whose
+    window (16 rows of 256 samples) holds it are zero, station 0's baselines keep N_c - 16
+    valid channel samples and the others all N_c (closed form; the flag path against the
+    oracle at 256 channels is in the flag tests)."""
     from paper_1801_04834_amd import binding
     w = _work(2, 1, 40, synth.CI16, synth.X_FP16_SPLIT, 2590)
-    _say("CASE c256 flags rejected")
+    _say("CASE c256 one lost sample")
+    G, g0, lost = 3, 1, 10 * C + 77                   # sample 77 of row 10 of station 0's window
     with binding.plan_for(w) as plan:
-        G = 3
         x = torch.from_numpy(synth.guarded_rows(w, 0, G)).cuda()
-        fl = torch.zeros((w.S, w.SB, plan.flag_words(w.N + G)), dtype=torch.int32, device="cuda")
-        with pytest.raises(binding.CobaltError) as ei:
-            plan.correlate_ex(x, w.delays(0), flags=fl)
-        assert ei.value.code == binding.EUNSUPPORTED
+        fl = np.zeros((w.S, w.SB, w.N + G), bool)
+        fl[0, 0, g0 + lost] = True
+        fd = torch.from_numpy(synth.pack_flags(fl).view(np.int32)).cuda()
         wts = torch.zeros(plan.weights_shape(), dtype=torch.int32, device="cuda")
-        plan.correlate_ex(x, w.delays(0), coarse=np.array([0, G], np.int32), weights=wts)
+        chan = plan.channelize_ex(x, w.delays(0), coarse=np.array([g0, 0], np.int32), flags=fd, weights=wts)
         torch.cuda.synchronize()
-        assert (wts.cpu().numpy() == 40).all()
+        hi, lo = unblock_planes(chan.cpu().numpy())
+        z0 = (hi[0, :, 0:2, :40] != 0).any(axis=(0, 1, 3))       # station 0, any channel / pol
+        assert not z0[10:26].any() and z0[:10].all() and z0[26:].all()
+        assert (hi[0, :, 2:4, :40] != 0).any(axis=(0, 1, 3)).all()
+        np.testing.assert_array_equal(wts.cpu().numpy()[0], [40 - 16, 40 - 16, 40])

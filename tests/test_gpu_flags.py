@@ -35,8 +35,8 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _work(S, SB, n_c, st, mode, seed):
-    return synth.Workload(name="flags", S=S, SB=SB, sample_type=st, x_mode=mode, N=64 * n_c,
+def _work(S, SB, n_c, st, mode, seed, C=64):
+    return synth.Workload(name="flags", S=S, SB=SB, sample_type=st, x_mode=mode, N=C * n_c, C=C,
                           sigma=16.0 if st == synth.CI8 else 64.0, seed=seed, delay_spread_s=1.5e-6,
                           delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5 if mode == synth.X_FP16_SPLIT else 0)
 
@@ -46,19 +46,23 @@ def _sequence(w, G, n_blocks, seed, flag_blocks):
     rows = [synth.guarded_rows(w, k, G) for k in range(n_blocks)]
     offs = [rng.integers(0, G + 1, w.S).astype(np.int32) for _ in range(n_blocks)]
     offs[0][0], offs[0][-1] = 0, G                     # both ends of the guard
-    flags = [synth.lost_sample_flags(seed + k, w.S, w.SB, w.N + G, p_packet=0.004, p_sample=0.0004,
+    # loss rates scaled by 64/C: a channel sample's FIR window spans 16 C input samples, so the
+    # same rates would flag most of a 256-channel block and leave sums of a handful of products
+    # (whose coherence error is not averaged down)
+    sc = 64 / w.C
+    flags = [synth.lost_sample_flags(seed + k, w.S, w.SB, w.N + G, p_packet=0.004 * sc, p_sample=0.0004 * sc,
                                      clean_stations=(1,)) if k in flag_blocks else None
              for k in range(n_blocks)]
     return rows, offs, flags
 
 
 def _oracle(w, rows, offs, flags):
-    hist = np.zeros((w.S, 2, w.SB, 15 * 64), np.complex128)
+    hist = np.zeros((w.S, 2, w.SB, 15 * w.C), np.complex128)
     hr = np.zeros((w.S, w.SB, 15), bool)
     outs = []
     for k in range(len(rows)):
         o = of.fx_block_flagged(synth.to_complex(rows[k]), w.N, offs[k], flags[k], hist, hr, w.fir(), w.bandpass(),
-                                w.subband_freqs(), synth.SAMPLE_RATE_HZ, w.delays(k), 64, 16, mode=MODE[w.x_mode],
+                                w.subband_freqs(), synth.SAMPLE_RATE_HZ, w.delays(k), w.C, 16, mode=MODE[w.x_mode],
                                 gain=w.gain())
         hist, hr = o["history"], o["hist_row_flags"]
         outs.append(o)
@@ -76,7 +80,7 @@ def _check_block(plan, w, chan, wts, vis, o, label):
     np.testing.assert_array_equal(W, o["W"], err_msg=f"{label}: weights")
     r = _chan(plan, chan)
     fl = np.repeat(o["chan_flags"].transpose(1, 0, 2), 2, axis=1)          # [SB, M, N_c]
-    fl = np.broadcast_to(fl[:, None], (w.SB, 64) + fl.shape[1:])
+    fl = np.broadcast_to(fl[:, None], (w.SB, w.C) + fl.shape[1:])
     n_fl = int(o["chan_flags"].sum())
     _say(f"  {label}: {n_fl} flagged channel samples (per station/subband), weights min {W.min()} of {n_c}")
     if plan.x_mode == synth.X_FP16_SPLIT:
@@ -130,15 +134,18 @@ def _eps(Vg, Vo, S):
     return worst
 
 
-@pytest.mark.parametrize("st,mode", [(synth.CI16, synth.X_FP16_SPLIT), (synth.CI16, synth.X_FP32),
-                                     (synth.CI8, synth.X_INT8), (synth.CF32, synth.X_FP32)])
+@pytest.mark.parametrize("st,mode,C", [(synth.CI16, synth.X_FP16_SPLIT, 64), (synth.CI16, synth.X_FP32, 64),
+                                       (synth.CI8, synth.X_INT8, 64), (synth.CF32, synth.X_FP32, 64),
+                                       (synth.CI16, synth.X_FP16_SPLIT, 256), (synth.CI8, synth.X_INT8, 256)])
 @pytest.mark.parametrize("n_c", [300, 8])
-def test_coarse_and_flagged_blocks_match_oracle(st, mode, n_c):
+def test_coarse_and_flagged_blocks_match_oracle(st, mode, C, n_c):
     from paper_1801_04834_amd import binding
     S, SB, G, nb = 5, 2, 37, 4
-    seed = 2100 + 10 * st + mode + n_c
-    w = _work(S, SB, n_c, st, mode, seed)
-    _say(f"CASE flags st={st} mode={mode} S={S} SB={SB} n_c={n_c} G={G} seed={seed}")
+    if C == 256:
+        n_c = n_c // 4 + 3                             # 78 and 5 channel samples of 256 inputs
+    seed = 2100 + 10 * st + mode + n_c + C
+    w = _work(S, SB, n_c, st, mode, seed, C)
+    _say(f"CASE flags st={st} mode={mode} C={C} S={S} SB={SB} n_c={n_c} G={G} seed={seed}")
     rows, offs, flags = _sequence(w, G, nb, seed, flag_blocks=(0, 1, 3))     # block 2 passes no flags
     outs = _oracle(w, rows, offs, flags)
     with binding.plan_for(w) as plan, binding.plan_for(w) as plan2:
