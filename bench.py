@@ -91,6 +91,9 @@ def parse():
                          "32/64/128 subbands, ci16/ci16/ci8), Poisson block arrivals, HBM-budget admission")
     ap.add_argument("--service-seconds", type=float, default=20.0)
     ap.add_argument("--service-budget-gib", type=float, default=48.0)
+    ap.add_argument("--mfma-probe-iters", type=int, default=16384,
+                    help="rounds of the dense MFMA probe (FP16 and int8, 512 workgroups), run first: the MFMA rate "
+                         "this GPU sustains under that load, reported as mfma_probe (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=1024,
                     help="plain device copy of this many MiB, run three times first: the HBM rate a streaming "
                          "kernel reaches (reported as hbm_copy_gbs) and the reference for counter calibration (0: skip)")
@@ -442,6 +445,23 @@ def main():
         log(f"bench: plain copy {n} B read + {n} B written in {ms:.3f} ms ({copy_gbs:.1f} GB/s)")
         del src, dst
 
+    probe = None
+    if args.mfma_probe_iters > 0:
+        sink = torch.empty(512 * 256, dtype=torch.float32, device=dev)
+        probe = {"workgroups": 512, "iterations": args.mfma_probe_iters}
+        for mode, name, k in ((synth.X_FP16_SPLIT, "fp16_tflops", 16), (synth.X_INT8, "int8_tops", 32)):
+            binding.mfma_probe(mode, 64, sink)                     # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ops = binding.mfma_probe(mode, args.mfma_probe_iters, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            if not bool(torch.all(sink == float(args.mfma_probe_iters * k))):
+                raise RuntimeError("MFMA probe returned wrong sums")
+            probe[name] = round(ops / (e0.elapsed_time(e1) * 1e-3) / 1e12, 1)
+        log(f"bench: MFMA probe {probe['fp16_tflops']} TFLOP/s FP16, {probe['int8_tops']} TOP/s int8 (dense, sustained)")
+        del sink
+
     plan = binding.plan_for(w)
     info = plan.info
     cmacs = info["useful_cmacs"]
@@ -496,6 +516,9 @@ def main():
               "peak": x_peak, "unit": x_unit, "frac": round(x_mfma_tflops / x_peak, 4),
               "traffic": measured_traffic(x_kernel), "kernel": x_kernel, "ms": round(x_ms_avg, 4),
               "operand_gbs": round(x_bytes / (x_ms_avg * 1e-3) / 1e9, 1)}
+    if probe is not None and w.x_mode != synth.X_FP32:
+        ref = probe["fp16_tflops"] if w.x_mode == synth.X_FP16_SPLIT else probe["int8_tops"]
+        x_roof["of_mfma_probe"] = round(x_mfma_tflops / ref, 4)
     dominant = f_roof if f_ms_avg >= x_ms_avg else x_roof
     other = x_roof if dominant is f_roof else f_roof
 
@@ -536,6 +559,8 @@ def main():
                              "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4),
                              "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}, 1>"),
                              "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1>"}}
+        if probe is not None:
+            beam["roofline"]["of_mfma_probe"] = round(mfma_tf / probe["fp16_tflops"], 4)
         log(f"bench: beamformer F {np.mean(bf_ms):.3f} ms + beams {b_ms:.3f} ms "
             f"({beam['beam_tcmacs']} TeraMAC/s useful, {mfma_tf:.0f} TFLOP/s executed)")
 
@@ -576,6 +601,7 @@ def main():
                              "deadline_ms": round(block_s * 1e3, 3)},
         "x_stage_tmacs": round(x_tmacs, 3),
         "hbm_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "mfma_probe": probe,
         "f_stage_gbs": round(f_gbs, 1),
         "roofline": dominant,
         "roofline_other": other,

@@ -252,6 +252,18 @@ int cobalt_apply_gains_adjoint(cobalt_plan* plan, const void* d_vis0, const void
  * operational readiness scripts, sec. 8).  Errors: EINVAL, EDEVICE. */
 int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
 
+/* Dense MFMA rate probe on the current device: `workgroups` workgroups of 256 threads (four
+ * waves; two workgroups fit a CU) each run `iterations` rounds of eight independent
+ * 32x32 MFMAs on register operands (x_mode COBALT_X_FP16_SPLIT: v_mfma_f32_32x32x16_f16,
+ * 32768 flop each; COBALT_X_INT8: v_mfma_i32_32x32x32_i8, 65536 ops each), so the launch does
+ * workgroups * 4 * iterations * 8 MFMAs.  Timed by the caller, it gives the MFMA rate the chip
+ * sustains at the clock it holds under that load, next to which kernel rates can be read (a
+ * readiness check, as the paper's operational scripts, sec. 8).  d_sink: device float
+ * [workgroups * 256]; every element receives iterations * K (K = 16 FP16, 32 int8), or -1 if
+ * a thread's accumulators disagree.  Errors: EINVAL (mode, iterations outside 1 .. 2^19,
+ * workgroups outside 1 .. 2^20, NULL or misaligned sink), EDEVICE. */
+int cobalt_mfma_probe(int32_t x_mode, int64_t iterations, int32_t workgroups, float* d_sink, void* stream);
+
 /* ---- streaming service --------------------------------------------------------------
  * ~1 s blocks from several concurrent observations.  Observations are admitted against an
  * HBM budget; blocks wait in a bounded FIFO per observation and run on the first free stream

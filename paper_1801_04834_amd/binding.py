@@ -25,7 +25,7 @@ _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW"
 EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_plan_query", "cobalt_correlate",
             "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
             "cobalt_beamform_channelized", "cobalt_correlate_channelized", "cobalt_reset_history",
-            "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_plan_destroy",
+            "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_mfma_probe", "cobalt_plan_destroy",
             "cobalt_last_error", "cobalt_service_create", "cobalt_service_open", "cobalt_service_submit",
             "cobalt_service_wait", "cobalt_service_pause", "cobalt_service_get_stats", "cobalt_service_close",
             "cobalt_service_destroy", "cobalt_service_last_error"]
@@ -99,6 +99,7 @@ def load_library():
     lib.cobalt_apply_gains.argtypes = [vp, vp, vp, vp, vp]
     lib.cobalt_apply_gains_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.cobalt_device_copy.argtypes = [vp, vp, ct.c_size_t, vp]
+    lib.cobalt_mfma_probe.argtypes = [i32, ct.c_int64, i32, vp, vp]
     lib.cobalt_plan_destroy.argtypes = [vp]
     lib.cobalt_last_error.argtypes = []
     lib.cobalt_last_error.restype = ct.c_char_p
@@ -157,6 +158,20 @@ def estimate_bytes(**kw) -> int:
     _check(load_library().cobalt_estimate_bytes(ct.byref(cfg), ct.byref(out)))
     del keep
     return int(out.value)
+
+
+def mfma_probe(x_mode, iterations, sink, stream=None):
+    """Dense MFMA rate probe (``cobalt_mfma_probe``): ``sink`` is a contiguous float32 device
+    tensor of workgroups * 256 elements; returns the number of MFMA operations (flop or int8
+    ops) the launch performs."""
+    import torch
+    if sink.dtype != torch.float32 or not sink.is_contiguous() or sink.numel() % 256:
+        raise ValueError("sink: contiguous float32, a multiple of 256 elements")
+    wgs = sink.numel() // 256
+    _check(load_library().cobalt_mfma_probe(int(x_mode), int(iterations), wgs, ct.c_void_p(sink.data_ptr()),
+                                            _stream_handle(torch, stream, sink.device)))
+    per = 32768 if x_mode == 1 else 65536
+    return wgs * 4 * int(iterations) * 8 * per
 
 
 def device_copy(dst, src, stream=None):

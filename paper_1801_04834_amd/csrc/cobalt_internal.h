@@ -82,6 +82,7 @@ hipError_t launch_weights(const uint32_t* cflag, int32_t* weights, int S, int SB
 hipError_t launch_beamformer(const BeamArgs& a, hipStream_t st);
 hipError_t launch_zero_fill(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
+hipError_t launch_mfma_probe(int x_mode, int64_t iters, int workgroups, float* sink, hipStream_t st);
 hipError_t launch_apply_gains(const void* vis0, const void* gains, void* vis, int n_chan, int S, hipStream_t st);
 hipError_t launch_apply_gains_adjoint(const void* vis0, const void* gains, const void* grad_vis, void* grad_gains, int n_chan,
                                       int S, hipStream_t st);

@@ -70,23 +70,7 @@ __global__ __launch_bounds__(256) void apply_gains_adjoint_kernel(const float2* 
     grad_gains[ch * M + k] = acc;
 }
 
-// Plain streaming copy, 16 bytes per lane: the reference kernel for calibrating HBM
-// traffic counters and for an HBM readiness check.
-__global__ __launch_bounds__(256) void device_copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n16) {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
-}
-
 }  // namespace
-
-hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st) {
-    const int64_t n16 = bytes / 16;
-    if (n16 == 0) return hipSuccess;
-    const int64_t blocks = (n16 + 255) / 256;
-    hipLaunchKernelGGL(device_copy_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st,
-                       (uint4*)dst, (const uint4*)src, n16);
-    return hipGetLastError();
-}
 
 hipError_t launch_apply_gains(const void* vis0, const void* gains, void* vis, int n_chan, int S, hipStream_t st) {
     const int64_t B = (int64_t)S * (S + 1) / 2;

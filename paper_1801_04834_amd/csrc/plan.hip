@@ -643,6 +643,19 @@ int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* strea
     return COBALT_OK;
 }
 
+int cobalt_mfma_probe(int32_t x_mode, int64_t iterations, int32_t workgroups, float* d_sink, void* stream) {
+    g_last_error.clear();
+    if (x_mode != COBALT_X_FP16_SPLIT && x_mode != COBALT_X_INT8)
+        return fail(COBALT_EINVAL, "x_mode must be FP16-split or int8 (got %d)", x_mode);
+    if (iterations < 1 || iterations > ((int64_t)1 << 19)) return fail(COBALT_EINVAL, "iterations must be 1 .. 2^19");
+    if (workgroups < 1 || workgroups > (1 << 20)) return fail(COBALT_EINVAL, "workgroups must be 1 .. 2^20");
+    if (!d_sink) return fail(COBALT_EINVAL, "NULL sink");
+    if ((uintptr_t)d_sink % 4) return fail(COBALT_EINVAL, "sink must be 4-byte aligned");
+    hipError_t e = launch_mfma_probe(x_mode, iterations, workgroups, d_sink, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "probe launch");
+    return COBALT_OK;
+}
+
 int cobalt_plan_destroy(cobalt_plan* p) {
     g_last_error.clear();
     if (!p) return COBALT_OK;

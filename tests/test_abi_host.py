@@ -113,3 +113,15 @@ def test_service_rejects_bad_arguments_before_touching_a_gpu(args):
     rc = lib.cobalt_service_create(ct.c_size_t(args[0]), args[1], args[2], ct.c_double(args[3]), ct.byref(out))
     assert rc == binding.EINVAL and not out.value
     assert lib.cobalt_service_last_error().decode()
+
+
+@pytest.mark.parametrize("mode,iters,wgs,sink", [(0, 10, 1, 256), (1, 0, 1, 256), (2, 2**19 + 1, 1, 256),
+                                                 (1, 10, 0, 256), (2, 10, 1, 0), (1, 10, 1, 258)])
+def test_mfma_probe_rejects_bad_arguments_before_touching_a_gpu(mode, iters, wgs, sink):
+    """FP32 mode, iterations outside 1 .. 2^19, no workgroups, a NULL or misaligned sink:
+    EINVAL from the argument checks (the sink pointers are never dereferenced)."""
+    import ctypes as ct
+    lib = _lib()
+    rc = lib.cobalt_mfma_probe(mode, ct.c_int64(iters), wgs, ct.c_void_p(sink), None)
+    assert rc == binding.EINVAL
+    assert lib.cobalt_last_error().decode()
