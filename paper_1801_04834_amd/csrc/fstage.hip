@@ -29,8 +29,10 @@ namespace {
 constexpr int kPass = 32;                 // channel samples per pass (= one K block)
 static_assert(kPass == kKBlock, "a pass writes exactly one K block per channel");
 constexpr int kChunk = kFChunk;           // channel samples per workgroup (8 passes)
-constexpr int kRowF2 = 68;                // LDS row: two 32-point halves, 16 B apart
+constexpr int kRowF2 = 68;                // complex staging row (float2): two 32-point halves, 16 B apart
 constexpr int kHalfF2 = 34;
+constexpr int kRowF1 = 72;                // split staging row (floats): conflict-free 16-byte column reads
+constexpr int kHalfF1 = 36;
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
@@ -208,9 +210,14 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
     using O_ = OutFmt<OM>;
     // per-wave FFT staging rows; for C = 256 the same memory first holds the radix-4
     // exchange (all waves' FIR outputs of the pass)
-    constexpr int kYl = kPass * kRowF2;
-    constexpr int kXch = kW > 1 ? kW * kPass * 64 : 0;
-    __shared__ float2 lds_f2[kW * kYl > kXch ? kW * kYl : kXch];
+    // FFT staging: 8-bit input (VALU-bound) stages real and imaginary parts in turn through a
+    // float buffer, halving the LDS per wave so that more waves fit a CU (measured 8.3 -> 7.9
+    // ms per 8-bit block); 16-bit and float input keep one complex buffer (the split costs
+    // them ~2 %).
+    constexpr bool kSplit = ST == ST_CI8;
+    constexpr int kYl = kSplit ? kPass * kRowF1 : 2 * kPass * kRowF2;   // floats per wave
+    constexpr int kXch = kW > 1 ? 2 * kW * kPass * 64 : 0;
+    __shared__ __attribute__((aligned(16))) float lds_f[kW * kYl > kXch ? kW * kYl : kXch];
     // Bandpass x mode scale per channel, staged in LDS: reading it from global memory in the
     // store loop would put a vector-memory wait on every channel, and such a wait also waits
     // for the prefetched rows of the next pass.  (The first pass's barrier orders this write.)
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
 
     const int lane = threadIdx.x & 63;
     const int wv = kW > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;   // wave index
-    float2* const ylds = lds_f2 + wv * kYl;
+    float* const ylds = lds_f + wv * kYl;
     // grid order: input row fastest, so neighbouring rows of one channel K block are
     // written by concurrently running waves (contiguous in the K-blocked layout)
     const int row_in = (int)(blockIdx.x % (unsigned)a.M);               // input index s*P + p
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
 
         // ---- C = 256: radix-4 stage across the four waves (bins k = 4k' + wv remain) ----
         if constexpr (kW > 1) {
-            float2* xch = lds_f2;                                     // [wave m][j][lane]
+            float2* xch = (float2*)lds_f;                             // [wave m][j][lane]
 #pragma unroll
             for (int j = 0; j < kPass; ++j) xch[(wv * kPass + j) * 64 + lane] = acc[j];
             __syncthreads();
@@ -358,31 +365,68 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
         }
 
         // ---- first DIF stage across lanes p, p+32 (two channel samples per swap) ----
-#pragma unroll
-        for (int pr = 0; pr < kPass / 2; ++pr) {
-            const float2 A = acc[2 * pr], B = acc[2 * pr + 1];
-            const auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.x), __float_as_uint(B.x), false, false);
-            const auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.y), __float_as_uint(B.y), false, false);
-            // lanes < 32: (y_j[q], y_j[q+32]) of j = 2pr; lanes >= 32: same for j = 2pr+1
-            const float r0r = __uint_as_float(sr[0]), r1r = __uint_as_float(sr[1]);
-            const float r0i = __uint_as_float(si[0]), r1i = __uint_as_float(si[1]);
-            const float dr = r0r - r1r, di = r0i - r1i;
-            const int row = 2 * pr + (lane >> 5), q = lane & 31;
-            ylds[row * kRowF2 + q] = make_float2(r0r + r1r, r0i + r1i);
-            ylds[row * kRowF2 + kHalfF2 + q] = make_float2(dr * wcs + di * wsn, di * wcs - dr * wsn);
-        }
-        __syncthreads();
-
-        // ---- 32-point DFT of the even (h = 0) or odd (h = 1) output bins ----
+        // The stage's outputs go through LDS to the lanes that own the 32-point DFTs.
         float xr[32], xi[32];
-        const float2* src = &ylds[jj * kRowF2 + hh * kHalfF2];
+        if constexpr (!kSplit) {
+            float2* const yl = (float2*)ylds;
 #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            const float2 v = src[q];
-            xr[q] = v.x;
-            xi[q] = v.y;
+            for (int pr = 0; pr < kPass / 2; ++pr) {
+                const float2 A = acc[2 * pr], B = acc[2 * pr + 1];
+                const auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.x), __float_as_uint(B.x), false, false);
+                const auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.y), __float_as_uint(B.y), false, false);
+                // lanes < 32: (y_j[q], y_j[q+32]) of j = 2pr; lanes >= 32: same for j = 2pr+1
+                const float r0r = __uint_as_float(sr[0]), r1r = __uint_as_float(sr[1]);
+                const float r0i = __uint_as_float(si[0]), r1i = __uint_as_float(si[1]);
+                const float dr = r0r - r1r, di = r0i - r1i;
+                const int row = 2 * pr + (lane >> 5), q = lane & 31;
+                yl[row * kRowF2 + q] = make_float2(r0r + r1r, r0i + r1i);
+                yl[row * kRowF2 + kHalfF2 + q] = make_float2(dr * wcs + di * wsn, di * wcs - dr * wsn);
+            }
+            __syncthreads();
+            // ---- 32-point DFT of the even (h = 0) or odd (h = 1) output bins ----
+            const float2* src = &yl[jj * kRowF2 + hh * kHalfF2];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const float2 v = src[q];
+                xr[q] = v.x;
+                xi[q] = v.y;
+            }
+            __syncthreads();
+        } else {
+            // real parts first, then imaginary parts, through one float buffer of 32 rows
+            float im_hold[kPass];              // imaginary outputs, stored after the real ones are read
+#pragma unroll
+            for (int pr = 0; pr < kPass / 2; ++pr) {
+                const float2 A = acc[2 * pr], B = acc[2 * pr + 1];
+                const auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.x), __float_as_uint(B.x), false, false);
+                const auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(A.y), __float_as_uint(B.y), false, false);
+                const float r0r = __uint_as_float(sr[0]), r1r = __uint_as_float(sr[1]);
+                const float r0i = __uint_as_float(si[0]), r1i = __uint_as_float(si[1]);
+                const float dr = r0r - r1r, di = r0i - r1i;
+                const int row = 2 * pr + (lane >> 5), q = lane & 31;
+                ylds[row * kRowF1 + q] = r0r + r1r;
+                ylds[row * kRowF1 + kHalfF1 + q] = dr * wcs + di * wsn;
+                im_hold[2 * pr] = r0i + r1i;
+                im_hold[2 * pr + 1] = di * wcs - dr * wsn;
+            }
+            __syncthreads();
+            // lane (jj, hh) reads row jj, half hh: with rows of 72 floats and halves 36 apart,
+            // any 16 lanes' 16-byte reads cover 64 distinct banks
+            const float* src = &ylds[jj * kRowF1 + hh * kHalfF1];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) xr[q] = src[q];
+            __syncthreads();
+#pragma unroll
+            for (int pr = 0; pr < kPass / 2; ++pr) {
+                const int row = 2 * pr + (lane >> 5), q = lane & 31;
+                ylds[row * kRowF1 + q] = im_hold[2 * pr];
+                ylds[row * kRowF1 + kHalfF1 + q] = im_hold[2 * pr + 1];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 32; ++q) xi[q] = src[q];
+            __syncthreads();
         }
-        __syncthreads();
         fft32(xr, xi);
 
         // ---- fine delay + bandpass, then write channel rows in ascending channel order ----

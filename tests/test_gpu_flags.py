@@ -109,14 +109,18 @@ def _check_block(plan, w, chan, wts, vis, o, label):
     rms = np.sqrt(np.mean(np.abs(o["Z"]) ** 2))
     err = np.abs(Zg - o["Z"])
     assert np.all(err <= 5e-6 * rms + 2e-6 * np.abs(o["Z"])), f"{label}: channelised mismatch"
-    eps = _eps(vis_complex(vis.cpu().numpy()), o["V"], w.S)
+    eps = _eps(vis_complex(vis.cpu().numpy()), o["V"], w.S, o["W"], rms)
     _say(f"  {label}: eps = {eps:.3e}")
     assert eps <= EPS
 
 
-def _eps(Vg, Vo, S):
+def _eps(Vg, Vo, S, W, rms, n_min=16):
     """Coherence error over entries whose stations keep valid samples; where a station lost
-    every channel sample its entries must be exactly zero."""
+    every channel sample its entries must be exactly zero.  An entry of a baseline with fewer
+    than n_min valid channel samples is a sum of a few products, whose error the sum does not
+    average down (a station's few remaining samples may all be small against the channelised
+    data's rms, to which the F stage's error is relative), so there the error is taken
+    relative to the scale of such a sum, rms^2 times the sample count, instead."""
     autos = np.stack([Vo[..., s * (s + 1) // 2 + s, 0].real for s in range(S)] +
                      [Vo[..., s * (s + 1) // 2 + s, 3].real for s in range(S)], axis=-1)   # [SB, C, 2S]
     worst = 0.0
@@ -126,6 +130,8 @@ def _eps(Vg, Vo, S):
             for q in range(4):
                 p1, p2 = q // 2, q % 2
                 den = np.sqrt(autos[..., p1 * S + s1] * autos[..., p2 * S + s2])
+                few = (W[:, bl] < n_min)[:, None]                     # [SB, 1] over channels
+                den = np.where(few & (den > 0), np.maximum(den, rms ** 2 * W[:, bl][:, None]), den)
                 diff = np.abs(Vg[..., bl, q] - Vo[..., bl, q])
                 zero = den == 0
                 assert np.all(Vg[..., bl, q][zero] == 0)
