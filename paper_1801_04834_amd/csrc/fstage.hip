@@ -214,9 +214,11 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
     // float buffer, halving the LDS per wave so that more waves fit a CU (measured 8.3 -> 7.9
     // ms per 8-bit block); 16-bit and float input keep one complex buffer (the split costs
     // them ~2 %).
-    constexpr bool kSplit = ST == ST_CI8;
+    constexpr bool kSplit = ST == ST_CI8 || C == 256;
     constexpr int kYl = kSplit ? kPass * kRowF1 : 2 * kPass * kRowF2;   // floats per wave
-    constexpr int kXch = kW > 1 ? 2 * kW * kPass * 64 : 0;
+    // the radix-4 exchange of C = 256 goes in two halves of the pass's channel samples
+    constexpr int kXj = kSplit ? kPass / 2 : kPass;
+    constexpr int kXch = kW > 1 ? 2 * kW * kXj * 64 : 0;
     __shared__ __attribute__((aligned(16))) float lds_f[kW * kYl > kXch ? kW * kYl : kXch];
     // Bandpass x mode scale per channel, staged in LDS: reading it from global memory in the
     // store loop would put a vector-memory wait on every channel, and such a wait also waits
@@ -338,30 +340,33 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
 
         // ---- C = 256: radix-4 stage across the four waves (bins k = 4k' + wv remain) ----
         if constexpr (kW > 1) {
-            float2* xch = (float2*)lds_f;                             // [wave m][j][lane]
+            float2* xch = (float2*)lds_f;                             // [wave m][j - j0][lane]
 #pragma unroll
-            for (int j = 0; j < kPass; ++j) xch[(wv * kPass + j) * 64 + lane] = acc[j];
-            __syncthreads();
+            for (int j0 = 0; j0 < kPass; j0 += kXj) {
 #pragma unroll
-            for (int j = 0; j < kPass; ++j) {
-                const float2 a0 = xch[(0 * kPass + j) * 64 + lane], a1 = xch[(1 * kPass + j) * 64 + lane];
-                const float2 a2 = xch[(2 * kPass + j) * 64 + lane], a3 = xch[(3 * kPass + j) * 64 + lane];
-                float zr, zi;
-                if (wv == 0) {
-                    zr = (a0.x + a2.x) + (a1.x + a3.x);
-                    zi = (a0.y + a2.y) + (a1.y + a3.y);
-                } else if (wv == 2) {
-                    zr = (a0.x + a2.x) - (a1.x + a3.x);
-                    zi = (a0.y + a2.y) - (a1.y + a3.y);
-                } else {
-                    // (a0 - a2) -+ i (a1 - a3) for wv = 1 / 3
-                    const float ur = a0.x - a2.x, ui = a0.y - a2.y, vr = a1.x - a3.x, vi = a1.y - a3.y;
-                    zr = wv == 1 ? ur + vi : ur - vi;
-                    zi = wv == 1 ? ui - vr : ui + vr;
+                for (int j = j0; j < j0 + kXj; ++j) xch[(wv * kXj + j - j0) * 64 + lane] = acc[j];
+                __syncthreads();
+#pragma unroll
+                for (int j = j0; j < j0 + kXj; ++j) {
+                    const float2 a0 = xch[(0 * kXj + j - j0) * 64 + lane], a1 = xch[(1 * kXj + j - j0) * 64 + lane];
+                    const float2 a2 = xch[(2 * kXj + j - j0) * 64 + lane], a3 = xch[(3 * kXj + j - j0) * 64 + lane];
+                    float zr, zi;
+                    if (wv == 0) {
+                        zr = (a0.x + a2.x) + (a1.x + a3.x);
+                        zi = (a0.y + a2.y) + (a1.y + a3.y);
+                    } else if (wv == 2) {
+                        zr = (a0.x + a2.x) - (a1.x + a3.x);
+                        zi = (a0.y + a2.y) - (a1.y + a3.y);
+                    } else {
+                        // (a0 - a2) -+ i (a1 - a3) for wv = 1 / 3
+                        const float ur = a0.x - a2.x, ui = a0.y - a2.y, vr = a1.x - a3.x, vi = a1.y - a3.y;
+                        zr = wv == 1 ? ur + vi : ur - vi;
+                        zi = wv == 1 ? ui - vr : ui + vr;
+                    }
+                    acc[j] = make_float2(zr * rtw_c + zi * rtw_s, zi * rtw_c - zr * rtw_s);
                 }
-                acc[j] = make_float2(zr * rtw_c + zi * rtw_s, zi * rtw_c - zr * rtw_s);
+                __syncthreads();                                      // the exchange is read before reuse
             }
-            __syncthreads();                                          // the exchange is read before ylds reuse
         }
 
         // ---- first DIF stage across lanes p, p+32 (two channel samples per swap) ----
