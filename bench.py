@@ -426,7 +426,7 @@ def main():
     torch.cuda.synchronize()
     log(f"bench: input {x.numel() * x.element_size() / 1e9:.2f} GB resident ({time.perf_counter() - t0:.1f} s)")
 
-    copy_gbs = None
+    copy_gbs = fanout_gbs = None
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 2**20
         src = torch.ones(n // 4, dtype=torch.float32, device=dev)
@@ -443,7 +443,18 @@ def main():
         ms = e0.elapsed_time(e1) / 3
         copy_gbs = 2 * n / (ms * 1e-3) / 1e9
         log(f"bench: plain copy {n} B read + {n} B written in {ms:.3f} ms ({copy_gbs:.1f} GB/s)")
-        del src, dst
+        # the same with two destinations: 1 byte read per 2 written, the 16-bit F stage's mix
+        dst2 = torch.empty_like(src)
+        binding.device_fanout(dst, dst2, src)
+        e0.record()
+        for _ in range(3):
+            binding.device_fanout(dst, dst2, src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        fanout_gbs = 3 * n / (ms * 1e-3) / 1e9
+        log(f"bench: fan-out copy {n} B read + {2 * n} B written in {ms:.3f} ms ({fanout_gbs:.1f} GB/s)")
+        del src, dst, dst2
 
     probe = None
     if args.mfma_probe_iters > 0:
@@ -512,6 +523,8 @@ def main():
                   "frac": round(f_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f_kernel), "kernel": f_kernel,
                   "ms": round(f_ms_avg, 4), "algorithmic_bytes": f_bytes,
                   "of_plain_copy": None if copy_gbs is None else round(f_gbs / copy_gbs, 4)}
+        if fanout_gbs is not None and chan_b == 2 * sample_b:
+            f_roof["of_same_mix_copy"] = round(f_gbs / fanout_gbs, 4)    # 1 read : 2 written
     x_roof = {"bound": "mfma" if w.x_mode != synth.X_FP32 else "alu", "achieved": round(x_mfma_tflops, 1),
               "peak": x_peak, "unit": x_unit, "frac": round(x_mfma_tflops / x_peak, 4),
               "traffic": measured_traffic(x_kernel), "kernel": x_kernel, "ms": round(x_ms_avg, 4),
@@ -601,6 +614,7 @@ def main():
                              "deadline_ms": round(block_s * 1e3, 3)},
         "x_stage_tmacs": round(x_tmacs, 3),
         "hbm_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "hbm_fanout_copy_gbs": None if fanout_gbs is None else round(fanout_gbs, 1),
         "mfma_probe": probe,
         "f_stage_gbs": round(f_gbs, 1),
         "roofline": dominant,

@@ -252,6 +252,12 @@ int cobalt_apply_gains_adjoint(cobalt_plan* plan, const void* d_vis0, const void
  * operational readiness scripts, sec. 8).  Errors: EINVAL, EDEVICE. */
 int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* stream);
 
+/* Copy of `bytes` from d_src to both d_dst0 and d_dst1 (multiples of 16; 16-byte aligned,
+ * non-overlapping): one byte read per two written, the HBM mix of an F stage that turns 4-byte
+ * input samples into 8-byte channelised ones, so its rate is the streaming reference for that
+ * kernel.  Errors: EINVAL, EDEVICE. */
+int cobalt_device_fanout(void* d_dst0, void* d_dst1, const void* d_src, size_t bytes, void* stream);
+
 /* Dense MFMA rate probe on the current device: `workgroups` workgroups of 256 threads (four
  * waves; two workgroups fit a CU) each run `iterations` rounds of eight independent
  * 32x32 MFMAs on register operands (x_mode COBALT_X_FP16_SPLIT: v_mfma_f32_32x32x16_f16,

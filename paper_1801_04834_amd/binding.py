@@ -25,7 +25,7 @@ _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW"
 EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_plan_query", "cobalt_correlate",
             "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
             "cobalt_beamform_channelized", "cobalt_correlate_channelized", "cobalt_reset_history",
-            "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_mfma_probe", "cobalt_plan_destroy",
+            "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_device_fanout", "cobalt_mfma_probe", "cobalt_plan_destroy",
             "cobalt_last_error", "cobalt_service_create", "cobalt_service_open", "cobalt_service_submit",
             "cobalt_service_wait", "cobalt_service_pause", "cobalt_service_get_stats", "cobalt_service_close",
             "cobalt_service_destroy", "cobalt_service_last_error"]
@@ -100,6 +100,7 @@ def load_library():
     lib.cobalt_apply_gains_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.cobalt_device_copy.argtypes = [vp, vp, ct.c_size_t, vp]
     lib.cobalt_mfma_probe.argtypes = [i32, ct.c_int64, i32, vp, vp]
+    lib.cobalt_device_fanout.argtypes = [vp, vp, vp, ct.c_size_t, vp]
     lib.cobalt_plan_destroy.argtypes = [vp]
     lib.cobalt_last_error.argtypes = []
     lib.cobalt_last_error.restype = ct.c_char_p
@@ -172,6 +173,17 @@ def mfma_probe(x_mode, iterations, sink, stream=None):
                                             _stream_handle(torch, stream, sink.device)))
     per = 32768 if x_mode == 1 else 65536
     return wgs * 4 * int(iterations) * 8 * per
+
+
+def device_fanout(dst0, dst1, src, stream=None):
+    """``src`` copied into both ``dst0`` and ``dst1`` (contiguous device tensors of equal size)."""
+    import torch
+    nb = src.numel() * src.element_size()
+    if any(t.numel() * t.element_size() != nb for t in (dst0, dst1)):
+        raise ValueError("size mismatch")
+    _check(load_library().cobalt_device_fanout(ct.c_void_p(dst0.data_ptr()), ct.c_void_p(dst1.data_ptr()),
+                                               ct.c_void_p(src.data_ptr()), nb, _stream_handle(torch, stream, src.device)))
+    return dst0, dst1
 
 
 def device_copy(dst, src, stream=None):

@@ -83,6 +83,7 @@ hipError_t launch_beamformer(const BeamArgs& a, hipStream_t st);
 hipError_t launch_zero_fill(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int x_mode, int64_t iters, int workgroups, float* sink, hipStream_t st);
+hipError_t launch_device_fanout(void* dst0, void* dst1, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_apply_gains(const void* vis0, const void* gains, void* vis, int n_chan, int S, hipStream_t st);
 hipError_t launch_apply_gains_adjoint(const void* vis0, const void* gains, const void* grad_vis, void* grad_gains, int n_chan,
                                       int S, hipStream_t st);

@@ -643,6 +643,16 @@ int cobalt_device_copy(void* d_dst, const void* d_src, size_t bytes, void* strea
     return COBALT_OK;
 }
 
+int cobalt_device_fanout(void* d_dst0, void* d_dst1, const void* d_src, size_t bytes, void* stream) {
+    g_last_error.clear();
+    if ((!d_dst0 || !d_dst1 || !d_src) && bytes > 0) return fail(COBALT_EINVAL, "NULL device pointer");
+    if (((uintptr_t)d_dst0 | (uintptr_t)d_dst1 | (uintptr_t)d_src | bytes) % 16)
+        return fail(COBALT_EINVAL, "pointers and size must be multiples of 16 bytes");
+    hipError_t e = launch_device_fanout(d_dst0, d_dst1, d_src, (int64_t)bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fan-out launch");
+    return COBALT_OK;
+}
+
 int cobalt_mfma_probe(int32_t x_mode, int64_t iterations, int32_t workgroups, float* d_sink, void* stream) {
     g_last_error.clear();
     if (x_mode != COBALT_X_FP16_SPLIT && x_mode != COBALT_X_INT8)

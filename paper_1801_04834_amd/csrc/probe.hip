@@ -1,7 +1,9 @@
 // Readiness probes: what this GPU sustains right now, measured beside every benchmark (the
 // paper checks each node with operational readiness scripts before use, sec. 8).
 //   device_copy_kernel: plain streaming copy, 16 bytes per lane; the HBM rate a streaming
-//   kernel can reach, and the reference for calibrating the HBM traffic counters.
+//   kernel can reach, and the reference for calibrating the HBM traffic counters.  With a
+//   second destination it writes every chunk twice: one byte read per two written, the mix
+//   of an F stage that turns 4-byte samples into 8-byte ones.
 //   mfma_probe_kernel: back-to-back dense MFMAs on register operands, eight independent
 //   accumulator chains per wave, two workgroups of four waves per CU; the MFMA rate at the
 //   clock the chip holds under that load.
@@ -18,6 +20,16 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void device_copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n16) {
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void device_fanout_kernel(uint4* __restrict__ dst0, uint4* __restrict__ dst1,
+                                                            const uint4* __restrict__ src, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
+        const uint4 v = src[i];
+        dst0[i] = v;
+        dst1[i] = v;
+    }
 }
 
 constexpr int kChains = 8;
@@ -70,6 +82,15 @@ hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStre
     const int64_t blocks = (n16 + 255) / 256;
     hipLaunchKernelGGL(device_copy_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st,
                        (uint4*)dst, (const uint4*)src, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_device_fanout(void* dst0, void* dst1, const void* src, int64_t bytes, hipStream_t st) {
+    const int64_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const int64_t blocks = (n16 + 255) / 256;
+    hipLaunchKernelGGL(device_fanout_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st,
+                       (uint4*)dst0, (uint4*)dst1, (const uint4*)src, n16);
     return hipGetLastError();
 }
 

@@ -125,3 +125,12 @@ def test_mfma_probe_rejects_bad_arguments_before_touching_a_gpu(mode, iters, wgs
     rc = lib.cobalt_mfma_probe(mode, ct.c_int64(iters), wgs, ct.c_void_p(sink), None)
     assert rc == binding.EINVAL
     assert lib.cobalt_last_error().decode()
+
+
+@pytest.mark.parametrize("ptrs,nbytes", [((0, 256, 512), 64), ((256, 256 + 8, 512), 64), ((256, 512, 768), 24)])
+def test_copies_reject_bad_arguments_before_touching_a_gpu(ptrs, nbytes):
+    """NULL or misaligned pointers and sizes that are not multiples of 16: EINVAL."""
+    import ctypes as ct
+    lib = _lib()
+    d0, d1, s = (ct.c_void_p(p) for p in ptrs)
+    assert lib.cobalt_device_fanout(d0, d1, s, ct.c_size_t(nbytes), None) == binding.EINVAL

@@ -35,3 +35,13 @@ def test_device_copy_moves_every_byte():
     binding.device_copy(dst, src)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+def test_device_fanout_writes_both_destinations():
+    from paper_1801_04834_amd import binding
+    _say("CASE device fan-out")
+    src = torch.randint(-2**31, 2**31 - 1, (2**20 + 8,), dtype=torch.int32, device="cuda")
+    d0, d1 = torch.zeros_like(src), torch.zeros_like(src)
+    binding.device_fanout(d0, d1, src)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, src) and torch.equal(d1, src)
