@@ -1,0 +1,84 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration the benchmark times
+(F stage then X stage on one plan over the whole block), checked on sampled subbands that the
+FP64 oracle computes on its own.
+
+* 16-bit share: 76 stations x 2 pol, 64 subbands, ci16, 196 608 samples, FP16-split X stage;
+  the visibilities of the first, a middle and the last subband against the oracle's, coherence
+  error <= 1e-5.
+* 8-bit mode: 76 stations x 2 pol, 128 subbands, ci8, int8 X stage; on the same three subbands
+  the requantised channelised data follow the +-1-at-a-rounding-boundary rule against the
+  oracle and the visibilities equal the exact integer correlation of the GPU's own int8 stream.
+
+Subbands are independent (each has its own streams, history and output), so the sampled ones
+stand for the rest; the whole block runs on the GPU as in the benchmark.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1801_04834_amd import synth
+from tests.layout import unblock
+from tests.metrics import coherence_error, near_rounding_boundary, vis_complex
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS_FP16 = 1e-5
+MODE = {synth.X_FP32: "fp32", synth.X_FP16_SPLIT: "fp16_split", synth.X_INT8: "int8"}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _input(w):
+    """The whole block on the device, generated on the host a few subbands at a time."""
+    dt = {synth.CI8: torch.int8, synth.CI16: torch.int16, synth.CF32: torch.float32}[w.sample_type]
+    x = torch.empty((w.S, 2, w.SB, w.N, 2), dtype=dt, device="cuda")
+    for sb0 in range(0, w.SB, 8):
+        sbs = list(range(sb0, min(w.SB, sb0 + 8)))
+        x[:, :, sb0:sb0 + len(sbs)].copy_(torch.from_numpy(w.block(0, subbands=sbs)))
+    return x
+
+
+def _oracle(w, sbs):
+    hist = np.zeros((w.S, 2, len(sbs), 15 * w.C), np.complex128)
+    return oracle.fx_block(synth.to_complex(w.block(0, subbands=sbs)), hist, w.fir(), w.bandpass(),
+                           w.subband_freqs()[sbs], synth.SAMPLE_RATE_HZ, w.delays(0), w.C, 16, mode=MODE[w.x_mode],
+                           gain=w.gain())
+
+
+@pytest.mark.parametrize("name", ["int16_share", "int8_full"])
+def test_full_size_block_on_sampled_subbands(name):
+    from paper_1801_04834_amd import binding
+    w = synth.workload(name)
+    sbs = [0, w.SB // 2 + 3, w.SB - 1]
+    _say(f"CASE fullsize {name} S={w.S} SB={w.SB} N={w.N} mode={w.x_mode} subbands={sbs} seed={w.seed}")
+    x = _input(w)
+    with binding.plan_for(w) as plan:
+        chan = plan.empty_chan()
+        vis = plan.empty_vis()
+        plan.channelize(x, w.delays(0), out=chan)
+        plan.correlate_channelized(chan, out=vis)
+        torch.cuda.synchronize()
+        del x
+        Vg = vis[sbs].cpu().numpy()
+        cg = chan[sbs].cpu().numpy() if w.x_mode == synth.X_INT8 else None
+    o = _oracle(w, sbs)
+    if w.x_mode == synth.X_INT8:
+        Qg = unblock(cg)[..., :w.n_c, :]
+        d = Qg.astype(np.int64) - o["Q"].astype(np.int64)
+        bad = d != 0
+        g = np.float64(np.float32(w.gain()))
+        pre = np.stack([(g * o["Zf"].real).astype(np.float32), (g * o["Zf"].imag).astype(np.float32)], -1)
+        _say(f"  int8 mismatches {int(bad.sum())} of {d.size}")
+        assert np.all(np.abs(d) <= 1) and np.all(near_rounding_boundary(pre, 1e-3)[bad])
+        np.testing.assert_array_equal(Vg.astype(np.int64), oracle.correlate_int(np.ascontiguousarray(Qg), w.S))
+    else:
+        eps = coherence_error(vis_complex(Vg), o["V"], w.S)
+        _say(f"  eps {eps:.3e}")
+        assert eps <= EPS_FP16
