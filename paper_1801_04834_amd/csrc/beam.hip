@@ -235,6 +235,7 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                 // the two lane halves; longer runs also span groups.  All register indices are
                 // compile-time; g and nS only select.
                 const int per = g >= 8 ? g / 8 : 1;
+                const bool full = tb + kBT <= a.n_c;            // no sample past N_c (uniform)
                 float part[NS] = {};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                     for (int u = 0; u < 4; ++u) {
                         const int r = 4 * q + u;
                         stokes(re[0][r], im[0][r], re[1][r], im[1][r], st[u]);
-                        if (tb + 8 * q + 4 * hb + u >= a.n_c)
+                        if (!full && tb + 8 * q + 4 * hb + u >= a.n_c)
 #pragma unroll
                             for (int k = 0; k < NS; ++k) st[u][k] = 0.f;
                     }

@@ -188,8 +188,9 @@ __device__ __forceinline__ float2 phasor_rev(double cyc) {
     return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }
 
-// Waves per SIMD each instantiation is compiled for: 3 where the registers fit without
-// spilling (64 channels), 2 otherwise; 256 channels are limited to 2 by LDS anyway.
+// Minimum waves per SIMD each instantiation is compiled for: 3 where the registers fit
+// without spilling, 2 otherwise (the compiled register counts allow 3 everywhere at present;
+// LDS then decides: 9 workgroups per CU for the complex FFT staging at 64 channels).
 template <int ST, int OM, int C>
 constexpr int fstage_waves() { return C == 64 && (ST == ST_CF32 || (ST == ST_CI16 && OM == XM_FP16_SPLIT)) ? 3 : 2; }
 
@@ -208,12 +209,12 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
     using S_ = Samp<ST>;
     using raw_t = typename S_::raw_t;
     using O_ = OutFmt<OM>;
-    // per-wave FFT staging rows; for C = 256 the same memory first holds the radix-4
-    // exchange (all waves' FIR outputs of the pass)
-    // FFT staging: 8-bit input (VALU-bound) stages real and imaginary parts in turn through a
-    // float buffer, halving the LDS per wave so that more waves fit a CU (measured 8.3 -> 7.9
-    // ms per 8-bit block); 16-bit and float input keep one complex buffer (the split costs
-    // them ~2 %).
+    // Per-wave FFT staging rows; for C = 256 the same memory first holds the radix-4
+    // exchange (all waves' FIR outputs of half a pass).  8-bit input (VALU-bound) and 256
+    // channels stage real and imaginary parts in turn through a float buffer, halving the LDS
+    // per wave so that more waves fit a CU (measured 8.3 -> 7.9 ms per 8-bit block, 3.79 ->
+    // 3.54 ms per 256-channel block); 16-bit and float input at 64 channels keep one complex
+    // buffer (the split costs them ~2 %).
     constexpr bool kSplit = ST == ST_CI8 || C == 256;
     constexpr int kYl = kSplit ? kPass * kRowF1 : 2 * kPass * kRowF2;   // floats per wave
     // the radix-4 exchange of C = 256 goes in two halves of the pass's channel samples
