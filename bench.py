@@ -403,8 +403,8 @@ def service_main(args, torch, binding, synth):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the FX chain shards over "
-              "subbands with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus must be 1 (the FX chain would shard over "
+              "subbands with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 

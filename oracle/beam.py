@@ -12,7 +12,7 @@ voltages of both polarisations or the Stokes parameters I or IQUV.  Incoherent b
 Stokes parameters per station first and then sum over stations.  Time resolution can be
 traded for frequency resolution within a subband.
 
-Readings (each listed in the design doc):
+Readings where the paper is silent:
 * channelisation, fine delay and bandpass exactly as ``fx.fx_block`` with C = 256;
 * beam weights ``w[b][s] = exp(+2 pi i f_c dtau[b][s])`` with ``dtau`` the extra arrival
   delay of beam b's direction at station s relative to the centre (same sign convention as

@@ -16,7 +16,7 @@ S stations (antenna fields), P = 2 polarisations, M = S*P inputs, SB subbands, C
 T FIR taps, N samples per subband per input per block, N_c = N / C channel samples,
 f_s the subband sample rate, h[T*C] the prototype FIR, b[C] the bandpass correction.
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 * FIR tap alignment: output j uses timeline rows j .. j+T-1 (the newest row last), i.e.
   ``y_j[p] = sum_t h[t*C + p] * x[(j - T + 1 + t)*C + p]`` over the block's own sample
   index, with the T-1 rows before the block taken from the carried history.

@@ -3,7 +3,7 @@
 Every case prints its name, sizes and seed before touching the GPU.  Inputs come from
 ``paper_1801_04834_amd.synth``; expected values come from ``oracle`` only.
 
-Tolerances (derivations in DESIGN.md):
+Tolerances:
 * FP16-split mode: coherence error eps <= 1e-5 (the required 16-bit-mode bound).
 * FP32 mode: eps <= 1e-5.  Sequential FP32 accumulation of N_c products leaves a relative
   error of about u*sqrt(N_c/3) (u = 2^-24), ~2e-6 rms at N_c = 3072, a few times that at
