@@ -226,3 +226,32 @@ def test_invalid_extras_are_rejected():
         v = plan.correlate_ex(x, w.delays(0), coarse=np.array([0, G], np.int32))
         torch.cuda.synchronize()
         assert torch.isfinite(v).all()
+
+
+def test_host_arrays_may_be_reused_as_soon_as_a_call_returns():
+    """Delays and coarse offsets are host arrays that the library copies before a call returns
+    (the kernels run later): overwriting them right after each call, while earlier work still
+    occupies the GPU, changes nothing."""
+    from paper_1801_04834_amd import binding
+    S, SB, n_c, G = 3, 1, 64, 17
+    w = _work(S, SB, n_c, synth.CI16, synth.X_FP16_SPLIT, 2204)
+    _say(f"CASE flags host arrays reused S={S} n_c={n_c} G={G}")
+    rows, offs, _ = _sequence(w, G, 3, 2204, flag_blocks=())
+    xs = [_dev(r) for r in rows]
+    with binding.plan_for(w) as p1, binding.plan_for(w) as p2:
+        ref = [p1.correlate_ex(xs[k], w.delays(k).copy(), coarse=offs[k].copy()).clone() for k in range(3)]
+        torch.cuda.synchronize()
+        a = torch.ones(2**28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            binding.device_copy(b, a)                   # ~2 ms of work queued ahead
+        got = []
+        for k in range(3):
+            d = np.ascontiguousarray(w.delays(k), np.float64)
+            o = np.ascontiguousarray(offs[k], np.int32)
+            got.append(p2.correlate_ex(xs[k], d, coarse=o))
+            d[:] = 3e-6                                 # the caller reuses its arrays at once
+            o[:] = G - o
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert torch.equal(ref[k], got[k])
