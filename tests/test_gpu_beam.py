@@ -63,7 +63,7 @@ def _check(label, coh, volt, inc, o):
 
 
 @pytest.mark.parametrize("S,NB,n_c,n_int,n_stokes", [(6, 37, 40, 1, 4), (6, 37, 40, 8, 4), (13, 130, 64, 64, 1),
-                                                     (48, 32, 96, 32, 4), (1, 1, 33, 1, 4)])
+                                                     (48, 32, 96, 32, 4), (1, 1, 33, 1, 4), (56, 40, 32, 16, 1)])
 def test_beamformer_matches_oracle(S, NB, n_c, n_int, n_stokes):
     from paper_1801_04834_amd import binding
     SB = 2
