@@ -45,8 +45,8 @@ def _oracle_run(w, blocks):
     return outs
 
 
-@pytest.mark.parametrize("st,mode", [(synth.CI16, synth.X_FP16_SPLIT), (synth.CI16, synth.X_FP32),
-                                     (synth.CI8, synth.X_INT8), (synth.CF32, synth.X_FP32)])
+@pytest.mark.parametrize("st", [synth.CI16, synth.CI8, synth.CF32])
+@pytest.mark.parametrize("mode", [synth.X_FP16_SPLIT, synth.X_FP32, synth.X_INT8])
 @pytest.mark.parametrize("n_c", [40, 300])
 def test_256_channels_match_oracle(st, mode, n_c):
     from paper_1801_04834_amd import binding
