@@ -138,7 +138,8 @@ def test_channelize_matches_oracle_two_blocks(st, mode, n_c):
 
 # ---------------------------------------------------------------- X stage only ----------
 
-@pytest.mark.parametrize("S,n_c", [(1, 64), (3, 100), (8, 3072), (16, 96), (76, 128), (80, 160)])
+@pytest.mark.parametrize("S,n_c", [(1, 64), (3, 100), (8, 3072), (16, 96), (24, 70), (44, 130), (60, 96), (76, 128),
+                                   (80, 160)])
 def test_x_int8_bit_exact(S, n_c):
     _say(f"CASE x_int8 S={S} n_c={n_c}")
     b = _binding()
@@ -169,7 +170,7 @@ def test_x_int8_overflow_bound_extremes():
         assert got[:, 0, 0, 0].max() == n_c * 2 * 127 ** 2
 
 
-@pytest.mark.parametrize("S,n_c", [(1, 32), (3, 100), (8, 1000), (40, 96), (76, 256), (80, 64)])
+@pytest.mark.parametrize("S,n_c", [(1, 32), (3, 100), (8, 1000), (24, 70), (40, 96), (60, 130), (76, 256), (80, 64)])
 def test_x_fp16_split_matches_oracle(S, n_c):
     _say(f"CASE x_fp16 S={S} n_c={n_c}")
     b = _binding()
