@@ -174,7 +174,6 @@ struct PassBuf<ST_CI8, C> {
 
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
-struct __attribute__((aligned(2))) char2_t { int8_t x, y; };
 
 template <int OM> struct OutFmt;
 template <> struct OutFmt<XM_FP32> { static constexpr int kPlanes = 1, kElem = 8; };
@@ -466,8 +465,11 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
             // the channel's base is wave-uniform (scalar adds); lane offsets are loop-invariant
             char* outq = out + (size_t)((uint32_t)(2 * kW * q) * cstride);
             char* dst = outq + lane_off;
+            // non-temporal stores: the channelised data is written once here and read once by
+            // the next kernel (measured 1-2 % faster than cached stores)
             if constexpr (OM == XM_FP32) {
-                *(float2*)dst = make_float2(zr, zi);
+                const float2v z2 = {zr, zi};
+                __builtin_nontemporal_store(z2, (float2v*)dst);
             } else if constexpr (OM == XM_FP16_SPLIT) {
                 // hi = fp16(z) (round to nearest even), lo = fp16(z - hi).  z - hi is exact in
                 // FP32, so v_fma_mix{lo,hi}_f16 (z + 1 * (-hi) with hi read as fp16, result
@@ -479,15 +481,13 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
                 unsigned lb;
                 asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lb) : "v"(zr), "v"(hb));
                 asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(lb) : "v"(zi), "v"(hb));
-                *(half2v*)dst = hi;
-                *(unsigned*)(outq + lane_off_lo) = lb;
+                __builtin_nontemporal_store(hb, (unsigned*)dst);
+                __builtin_nontemporal_store(lb, (unsigned*)(outq + lane_off_lo));
             } else {
                 const float qr = fminf(fmaxf(rintf(zr), -127.f), 127.f);
                 const float qi = fminf(fmaxf(rintf(zi), -127.f), 127.f);
-                char2_t v;
-                v.x = (int8_t)(int)qr;
-                v.y = (int8_t)(int)qi;
-                *(char2_t*)dst = v;
+                const unsigned short v = (unsigned short)(((unsigned)(int)qr & 0xffu) | (((unsigned)(int)qi & 0xffu) << 8));
+                __builtin_nontemporal_store(v, (unsigned short*)dst);
             }
             if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // bound live ranges per 4 channels
         }
