@@ -1,9 +1,11 @@
 // Readiness probes: what this GPU sustains right now, measured beside every benchmark (the
 // paper checks each node with operational readiness scripts before use, sec. 8).
-//   device_copy_kernel: plain streaming copy, 16 bytes per lane; the HBM rate a streaming
-//   kernel can reach, and the reference for calibrating the HBM traffic counters.  With a
-//   second destination it writes every chunk twice: one byte read per two written, the mix
-//   of an F stage that turns 4-byte samples into 8-byte ones.
+//   device_copy_kernel: plain streaming copy, 16 bytes per lane, one element per lane and as
+//   many workgroups as elements / 256, so the running workgroups sweep memory in order (a
+//   grid-stride loop over a fixed grid measured ~12 % slower); the HBM rate a streaming kernel
+//   can reach, and the reference for calibrating the HBM traffic counters.  With a second
+//   destination it writes every chunk twice: one byte read per two written, the mix of an F
+//   stage that turns 4-byte samples into 8-byte ones.
 //   mfma_probe_kernel: back-to-back dense MFMAs on register operands, eight independent
 //   accumulator chains per wave, two workgroups of four waves per CU; the MFMA rate at the
 //   clock the chip holds under that load.
@@ -79,8 +81,8 @@ __global__ __launch_bounds__(256, 2) void mfma_probe_kernel(int64_t iters, float
 hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st) {
     const int64_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;
-    const int64_t blocks = (n16 + 255) / 256;
-    hipLaunchKernelGGL(device_copy_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st,
+    const int64_t blocks = (n16 + 255) / 256;   // the loop in the kernel covers sizes beyond 2^30 workgroups
+    hipLaunchKernelGGL(device_copy_kernel, dim3((unsigned)(blocks < (1 << 30) ? blocks : (1 << 30))), dim3(256), 0, st,
                        (uint4*)dst, (const uint4*)src, n16);
     return hipGetLastError();
 }
@@ -89,7 +91,7 @@ hipError_t launch_device_fanout(void* dst0, void* dst1, const void* src, int64_t
     const int64_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;
     const int64_t blocks = (n16 + 255) / 256;
-    hipLaunchKernelGGL(device_fanout_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st,
+    hipLaunchKernelGGL(device_fanout_kernel, dim3((unsigned)(blocks < (1 << 30) ? blocks : (1 << 30))), dim3(256), 0, st,
                        (uint4*)dst0, (uint4*)dst1, (const uint4*)src, n16);
     return hipGetLastError();
 }
