@@ -8,6 +8,8 @@ FP64 oracle computes on its own.
 * 8-bit mode: 76 stations x 2 pol, 128 subbands, ci8, int8 X stage; on the same three subbands
   the requantised channelised data follow the +-1-at-a-rounding-boundary rule against the
   oracle and the visibilities equal the exact integer correlation of the GPU's own int8 stream.
+* plain FP32 form of the 16-bit share (FP32 channelised data, FP32 VALU X stage): coherence
+  error <= 1e-5 on the same three subbands.
 
 Subbands are independent (each has its own streams, history and output), so the sampled ones
 stand for the rest; the whole block runs on the GPU as in the benchmark.
@@ -27,6 +29,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 EPS_FP16 = 1e-5
+EPS_FP32 = 1e-5
 MODE = {synth.X_FP32: "fp32", synth.X_FP16_SPLIT: "fp16_split", synth.X_INT8: "int8"}
 
 
@@ -52,10 +55,10 @@ def _oracle(w, sbs):
                            gain=w.gain())
 
 
-@pytest.mark.parametrize("name", ["int16_share", "int8_full"])
-def test_full_size_block_on_sampled_subbands(name):
+@pytest.mark.parametrize("name,mode", [("int16_share", None), ("int8_full", None), ("int16_share", synth.X_FP32)])
+def test_full_size_block_on_sampled_subbands(name, mode):
     from paper_1801_04834_amd import binding
-    w = synth.workload(name)
+    w = synth.workload(name) if mode is None else synth.workload(name, x_mode=mode)
     sbs = [0, w.SB // 2 + 3, w.SB - 1]
     _say(f"CASE fullsize {name} S={w.S} SB={w.SB} N={w.N} mode={w.x_mode} subbands={sbs} seed={w.seed}")
     x = _input(w)
@@ -81,4 +84,4 @@ def test_full_size_block_on_sampled_subbands(name):
     else:
         eps = coherence_error(vis_complex(Vg), o["V"], w.S)
         _say(f"  eps {eps:.3e}")
-        assert eps <= EPS_FP16
+        assert eps <= (EPS_FP32 if w.x_mode == synth.X_FP32 else EPS_FP16)
