@@ -10,6 +10,9 @@ FP64 oracle computes on its own.
   oracle and the visibilities equal the exact integer correlation of the GPU's own int8 stream.
 * plain FP32 form of the 16-bit share (FP32 channelised data, FP32 VALU X stage): coherence
   error <= 1e-5 on the same three subbands.
+* the benchmark's flagged 16-bit share (rows with a 2048-sample guard, per-station coarse
+  offsets across it, 16-sample packets lost with probability 0.2 %) through the full chain with
+  weights: weights exact and coherence error <= 1e-5 on the same three subbands.
 
 Subbands are independent (each has its own streams, history and output), so the sampled ones
 stand for the rest; the whole block runs on the GPU as in the benchmark.
@@ -85,3 +88,41 @@ def test_full_size_block_on_sampled_subbands(name, mode):
         eps = coherence_error(vis_complex(Vg), o["V"], w.S)
         _say(f"  eps {eps:.3e}")
         assert eps <= (EPS_FP32 if w.x_mode == synth.X_FP32 else EPS_FP16)
+
+
+def test_full_size_coarse_delay_and_flags_on_sampled_subbands():
+    from paper_1801_04834_amd import binding
+    from oracle import flags as oflags
+    from tests.test_gpu_flags import _eps
+    w = synth.workload("int16_share")
+    G = 2048
+    sbs = [0, w.SB // 2 + 3, w.SB - 1]
+    _say(f"CASE fullsize flagged int16_share S={w.S} SB={w.SB} N={w.N} G={G} subbands={sbs} seed={w.seed}")
+    x = _input(w)
+    xg = torch.empty((w.S, 2, w.SB, w.N + G, 2), dtype=x.dtype, device="cuda")
+    xg[:, :, :, :w.N].copy_(x)
+    xg[:, :, :, w.N:].copy_(x[:, :, :, :G])             # the guard repeats the block's first samples
+    del x
+    offs = np.random.default_rng([w.seed, 0xC0]).integers(0, G + 1, w.S).astype(np.int32)
+    fl = synth.lost_sample_flags(w.seed, w.S, w.SB, w.N + G, p_packet=0.002, p_sample=0.0)
+    fd = torch.from_numpy(synth.pack_flags(fl).view(np.int32)).to("cuda")
+    with binding.plan_for(w) as plan:
+        wts = torch.full(plan.weights_shape(), -1, dtype=torch.int32, device="cuda")
+        vis = plan.correlate_ex(xg, w.delays(0), coarse=offs, flags=fd, weights=wts)
+        torch.cuda.synchronize()
+        Vg = vis[sbs].cpu().numpy()
+        Wg = wts[sbs].cpu().numpy()
+    del xg, fd, vis
+    blk = w.block(0, subbands=sbs)
+    rows = np.concatenate([blk, blk[:, :, :, :G]], axis=3)
+    hist = np.zeros((w.S, 2, len(sbs), 15 * w.C), np.complex128)
+    hrow = np.zeros((w.S, len(sbs), 15), bool)
+    o = oflags.fx_block_flagged(synth.to_complex(rows), w.N, offs, fl[:, sbs], hist, hrow, w.fir(), w.bandpass(),
+                                w.subband_freqs()[sbs], synth.SAMPLE_RATE_HZ, w.delays(0), w.C, 16,
+                                mode=MODE[w.x_mode], gain=w.gain())
+    _say(f"  lost {float(fl.mean()):.4%} of the samples, weights min {Wg.min()} of {w.n_c}")
+    np.testing.assert_array_equal(Wg, o["W"])
+    rms = np.sqrt(np.mean(np.abs(o["Z"]) ** 2))
+    eps = _eps(vis_complex(Vg), o["V"], w.S, o["W"], rms)
+    _say(f"  eps {eps:.3e}")
+    assert eps <= EPS_FP16
