@@ -13,6 +13,10 @@ FP64 oracle computes on its own.
 * the benchmark's flagged 16-bit share (rows with a 2048-sample guard, per-station coarse
   offsets across it, 16-sample packets lost with probability 0.2 %) through the full chain with
   weights: weights exact and coherence error <= 1e-5 on the same three subbands.
+* the benchmark's beamformer workload (48 stations x 2 pol, 61 subbands, 256 channels, 127
+  coherent beams, Stokes I over 16 channel samples, incoherent Stokes I), F stage then the
+  beamformer as the benchmark runs them: coherent and incoherent Stokes of three sampled
+  subbands within |dS| <= 2e-5 I + 1e-6 mean(I) of the oracle's.
 
 Subbands are independent (each has its own streams, history and output), so the sampled ones
 stand for the rest; the whole block runs on the GPU as in the benchmark.
@@ -126,3 +130,35 @@ def test_full_size_coarse_delay_and_flags_on_sampled_subbands():
     eps = _eps(vis_complex(Vg), o["V"], w.S, o["W"], rms)
     _say(f"  eps {eps:.3e}")
     assert eps <= EPS_FP16
+
+
+def test_full_size_beamformer_on_sampled_subbands():
+    from paper_1801_04834_amd import binding
+    from oracle import beam as obeam
+    w = synth.Workload(name="beam_share", S=48, SB=61, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, C=256,
+                       sigma=64.0, seed=1807, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05,
+                       fp16_prescale_log2=5)
+    NB, n_int = 127, 16
+    sbs = [0, w.SB // 2, w.SB - 1]
+    _say(f"CASE fullsize beamformer S={w.S} SB={w.SB} C={w.C} NB={NB} n_int={n_int} subbands={sbs} seed={w.seed}")
+    dtau = np.random.default_rng(1808).uniform(-2e-6, 2e-6, (NB, w.S))
+    x = _input(w)
+    with binding.plan_for(w) as plan:
+        cs, _, isz = plan.beam_shapes(NB, 1, n_int)
+        coh = torch.full(cs, np.nan, dtype=torch.float32, device="cuda")
+        inc = torch.full(isz, np.nan, dtype=torch.float32, device="cuda")
+        chan = plan.channelize(x, w.delays(0))
+        plan.beamform_channelized(chan, torch.from_numpy(dtau).cuda(), 1, n_int, coherent=coh, incoherent=inc)
+        torch.cuda.synchronize()
+        del x, chan
+        cg = coh[sbs].cpu().numpy().transpose(0, 1, 4, 3, 2)      # -> [SB, C, NB, 1, n_out]
+        ig = inc[sbs].cpu().numpy().transpose(0, 1, 3, 2)         # -> [SB, C, 1, n_out]
+    hist = np.zeros((w.S, 2, len(sbs), 15 * w.C), np.complex128)
+    o = obeam.beamform_block(synth.to_complex(w.block(0, subbands=sbs)), hist, w.fir(), w.bandpass(),
+                             w.subband_freqs()[sbs], synth.SAMPLE_RATE_HZ, w.delays(0), dtau, w.C, 16, which="I",
+                             n_int=n_int)
+    for name, got, want in (("coherent", cg, o["coherent"]), ("incoherent", ig, o["incoherent"])):
+        err = np.abs(got.astype(np.float64) - want)
+        worst = float(np.max(err / (np.abs(want) + np.mean(np.abs(want)))))
+        _say(f"  {name}: worst {worst:.3e}")
+        assert np.all(err <= 2e-5 * np.abs(want) + 1e-6 * np.mean(np.abs(want))), f"{name} off, worst {worst:.3e}"
