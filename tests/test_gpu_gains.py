@@ -35,7 +35,7 @@ def _gains(rng, shape):
     return (rng.uniform(0.5, 1.5, shape) * np.exp(1j * rng.uniform(-np.pi, np.pi, shape))).astype(np.complex64)
 
 
-@pytest.mark.parametrize("S,SB", [(1, 1), (5, 2), (48, 1), (80, 1)])
+@pytest.mark.parametrize("S,SB", [(1, 1), (5, 2), (48, 1), (80, 1), (48, 16)])
 def test_apply_and_adjoint_match_oracle(S, SB):
     _say(f"CASE gains S={S} SB={SB}")
     rng = np.random.default_rng(S * 10 + SB)
