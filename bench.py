@@ -203,7 +203,7 @@ def time_beamformer(torch, binding, synth, steps, device):
     per-step F-stage and beamformer times (ms) and the workload's sizes."""
     w = synth.Workload(name="beam_share", S=48, SB=61, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, C=256,
                        sigma=64.0, seed=1807, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05,
-                       fp16_prescale_log2=5)
+                       fp16_prescale_log2=-1)
     NB, n_int = 127, 16
     x = make_input(w, torch, device)
     plan = binding.plan_for(w)
@@ -236,7 +236,7 @@ def time_gains(torch, binding, synth, steps, device):
     one correlated block, then per step the gain forward (V' = g_a conj(g_b) V0) and the
     hand-written adjoint (dL/dg for an upstream gradient of V's shape)."""
     w = synth.Workload(name="gains_48", S=48, SB=16, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, sigma=64.0,
-                       seed=1809, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5)
+                       seed=1809, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1)
     plan = binding.plan_for(w)
     x = make_input(w, torch, device)
     vis0 = torch.view_as_complex(plan.correlate(x, w.delays(0)))
@@ -311,9 +311,9 @@ def service_main(args, torch, binding, synth):
     import threading
     block_s = synth.BLOCK_SAMPLES / synth.SAMPLE_RATE_HZ
     ws = [synth.Workload(name="O1", S=24, SB=32, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1805,
-                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5),
+                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1),
           synth.Workload(name="O2", S=48, SB=64, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1806,
-                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5),
+                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1),
           synth.Workload(name="O3", S=76, SB=128, sample_type=synth.CI8, x_mode=synth.X_INT8, sigma=16.0, seed=1807,
                          delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05)]
     t0 = time.perf_counter()

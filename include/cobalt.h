@@ -71,7 +71,8 @@ extern "C" {
 #define COBALT_OK            0
 #define COBALT_EINVAL       -1   /* bad argument: sizes, NULL pointers, N % C != 0 ...   */
 #define COBALT_EUNSUPPORTED -2   /* valid but not built: C not 64/256, T != 16, P != 2, M > 160 in MFMA modes */
-#define COBALT_EOVERFLOW    -3   /* INT8 mode with N_c * 2 * 127^2 >= 2^31 (int32 sums)   */
+#define COBALT_EOVERFLOW    -3   /* INT8 mode with N_c * 2 * 127^2 >= 2^31 (int32 sums), or an
+                                    FP16-split prescale that full-scale samples would overflow */
 #define COBALT_ENOMEM       -4   /* device or pinned host allocation failed              */
 #define COBALT_EBUSY        -5   /* another host thread is inside a call on this plan    */
 #define COBALT_EDEVICE      -6   /* HIP runtime error; see cobalt_last_error()           */
@@ -97,7 +98,12 @@ typedef struct cobalt_config {
     int32_t sample_type;         /* COBALT_CI8 | COBALT_CI16 | COBALT_CF32                */
     int32_t x_mode;              /* COBALT_X_FP32 | COBALT_X_FP16_SPLIT | COBALT_X_INT8   */
     int32_t fp16_prescale_log2;  /* k in [-24, 24]: FP16-split stores 2^k * Z; V is scaled
-                                    back by 2^-2k (exact).  Ignored in other modes.       */
+                                    back by 2^-2k (exact).  Ignored in other modes.  For
+                                    CI8 / CI16 samples k must not exceed the bound that
+                                    cobalt_fp16_prescale_max reports (else EOVERFLOW), so
+                                    no valid input overflows FP16; for CF32 samples the
+                                    caller keeps 2^k |Z| <= 65504, larger components are
+                                    stored saturated at +-65504.                          */
     int64_t samples_per_block;   /* N >= 0, multiple of C (196608 for ~1 s blocks)        */
     double  sample_rate_hz;      /* f_s > 0, subband sample rate (195312.5)               */
     float   requant_gain;        /* g > 0: INT8 mode stores clamp(rint(g * Z), +-127)      */
@@ -129,6 +135,19 @@ int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out);
 /* Device bytes cobalt_plan_create would allocate for cfg (for admission by HBM budget).
  * Performs the same validation as create.  Allocates nothing. */
 int cobalt_estimate_bytes(const cobalt_config* cfg, size_t* device_bytes);
+
+/* Largest fp16_prescale_log2 for which no CI8 / CI16 input can overflow FP16 in the
+ * FP16-split channelised data (sec. 3.2: the fixed-point samples become floats before the
+ * chain).  Every channel sample satisfies |Z| <= max_c |b_c| * sum_m |h[m]| * max|x|, with
+ * max|x| = 2^15 sqrt(2) (CI16) or 2^7 sqrt(2) (CI8), by the triangle inequality through
+ * FIR, DFT, unit-modulus delay phasor and bandpass; an input matched to the signs of the
+ * taps reaches it.  *k_max is the largest k with 2^k * bound * (1 + 2^-10) <= 65504, at
+ * most 24 (the margin covers the F stage's FP32 rounding).  With the Blackman-windowed sinc
+ * of 16 taps (sum |h| = 1.60) and a bandpass peaking at 1.05 this is -1 for CI16 and 7 for
+ * CI8.  cfg is validated as for cobalt_plan_create (its x_mode and prescale are ignored).
+ * Allocates nothing.  Errors: EINVAL (NULL, invalid cfg, CF32 samples: no fixed bound),
+ * EUNSUPPORTED, EOVERFLOW (no k >= -24 is safe). */
+int cobalt_fp16_prescale_max(const cobalt_config* cfg, int32_t* k_max);
 
 /* Fill *info with the plan's sizes.  Errors: EINVAL (NULL). */
 int cobalt_plan_query(const cobalt_plan* plan, cobalt_plan_info* info);

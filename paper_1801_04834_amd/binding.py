@@ -22,7 +22,7 @@ COBALT_OK, EINVAL, EUNSUPPORTED, EOVERFLOW, ENOMEM, EBUSY, EDEVICE = 0, -1, -2, 
 _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM",
           EBUSY: "EBUSY", EDEVICE: "EDEVICE"}
 
-EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_plan_query", "cobalt_correlate",
+EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_fp16_prescale_max", "cobalt_plan_query", "cobalt_correlate",
             "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
             "cobalt_beamform_channelized", "cobalt_correlate_channelized", "cobalt_reset_history",
             "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_device_fanout", "cobalt_mfma_probe", "cobalt_plan_destroy",
@@ -87,6 +87,7 @@ def load_library():
     vp, i32 = ct.c_void_p, ct.c_int
     lib.cobalt_plan_create.argtypes = [ct.POINTER(Config), ct.POINTER(vp)]
     lib.cobalt_estimate_bytes.argtypes = [ct.POINTER(Config), ct.POINTER(ct.c_size_t)]
+    lib.cobalt_fp16_prescale_max.argtypes = [ct.POINTER(Config), ct.POINTER(ct.c_int32)]
     lib.cobalt_plan_query.argtypes = [vp, ct.POINTER(PlanInfo)]
     lib.cobalt_correlate.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
     lib.cobalt_channelize.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
@@ -157,6 +158,16 @@ def estimate_bytes(**kw) -> int:
     cfg, keep = make_config(**kw)
     out = ct.c_size_t(0)
     _check(load_library().cobalt_estimate_bytes(ct.byref(cfg), ct.byref(out)))
+    del keep
+    return int(out.value)
+
+
+def fp16_prescale_max(**kw) -> int:
+    """Largest ``fp16_prescale_log2`` for which no 8/16-bit input of this setting can overflow
+    FP16 (``cobalt_fp16_prescale_max``)."""
+    cfg, keep = make_config(**kw)
+    out = ct.c_int32(0)
+    _check(load_library().cobalt_fp16_prescale_max(ct.byref(cfg), ct.byref(out)))
     del keep
     return int(out.value)
 

@@ -475,12 +475,21 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(fstage_waves<
                 // FP32, so v_fma_mix{lo,hi}_f16 (z + 1 * (-hi) with hi read as fp16, result
                 // rounded once to fp16) gives the same bits as converting hi back, subtracting
                 // and converting, in one instruction per component.
-                const float2v z2 = {zr, zi};
+                // Integer samples cannot overflow FP16 here: plan creation bounds the prescale
+                // by the largest channel sample full-scale input can produce.  Float samples
+                // have no such bound, so their components saturate at the largest FP16 value
+                // instead of turning into infinities.
+                float zr_ = zr, zi_ = zi;
+                if constexpr (ST == ST_CF32) {
+                    zr_ = __builtin_amdgcn_fmed3f(zr, -65504.f, 65504.f);
+                    zi_ = __builtin_amdgcn_fmed3f(zi, -65504.f, 65504.f);
+                }
+                const float2v z2 = {zr_, zi_};
                 const half2v hi = __builtin_convertvector(z2, half2v);
                 const unsigned hb = __builtin_bit_cast(unsigned, hi);
                 unsigned lb;
-                asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lb) : "v"(zr), "v"(hb));
-                asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(lb) : "v"(zi), "v"(hb));
+                asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lb) : "v"(zr_), "v"(hb));
+                asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(lb) : "v"(zi_), "v"(hb));
                 __builtin_nontemporal_store(hb, (unsigned*)dst);
                 __builtin_nontemporal_store(lb, (unsigned*)(outq + lane_off_lo));
             } else {

@@ -46,6 +46,32 @@ struct Sizes {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Largest power-of-two prescale k for which no channelised value of an integer sample type
+// can overflow FP16.  Integer samples are converted to float exactly (sec. 3.2), so every
+// component of a channel sample is bounded by the triangle inequality through the chain:
+//   |Z| = |b_c| |X_k| <= max|b| sum_p |y_j[p]| <= max|b| sum_m |h[m]| max|x|,
+// with max|x| = 2^15 sqrt(2) (int16) or 2^7 sqrt(2) (int8) for the complex sample
+// (-2^15, -2^15) resp. (-2^7, -2^7); the delay phasor has unit modulus.  A sign-matched
+// input (x = sgn(h) (1 + i) 2^15 over one FIR window) reaches the bound in the channel of
+// FFT bin 0.  FP16 round-to-nearest overflows at 65520; the 2^-10 margin covers the F
+// stage's FP32 rounding on the way.  Returns INT32_MIN when the sample type has no bound
+// (float samples).
+int fp16_prescale_limit(const cobalt_config* c) {
+    if (c->sample_type == COBALT_CF32) return INT32_MIN;
+    double sh = 0.0;
+    for (int i = 0; i < c->n_taps * c->n_channels; ++i) sh += std::fabs((double)c->h_fir[i]);
+    double bmax = 1.0;
+    if (c->h_bandpass) {
+        bmax = 0.0;
+        for (int i = 0; i < c->n_channels; ++i) bmax = std::fmax(bmax, std::fabs((double)c->h_bandpass[i]));
+    }
+    const double xmax = (c->sample_type == COBALT_CI8 ? 128.0 : 32768.0) * std::sqrt(2.0);
+    const double bound = bmax * sh * xmax * (1.0 + std::ldexp(1.0, -10));
+    if (!(bound > 0.0)) return 24;                  // all-zero taps or bandpass: nothing can grow
+    const int k = (int)std::floor(std::log2(65504.0 / bound));
+    return k > 24 ? 24 : k;
+}
+
 int validate(const cobalt_config* c, Sizes* z) {
     if (!c) return fail(COBALT_EINVAL, "cfg is NULL");
     if (c->n_stations < 1) return fail(COBALT_EINVAL, "n_stations must be >= 1 (got %d)", c->n_stations);
@@ -95,8 +121,16 @@ int validate(const cobalt_config* c, Sizes* z) {
             return fail(COBALT_EOVERFLOW, "INT8 mode: N_c * 2 * 127^2 = %lld overflows int32 (N_c = %lld)",
                         (long long)(s.n_c * 2 * 127 * 127), (long long)s.n_c);
     }
-    if (c->x_mode == COBALT_X_FP16_SPLIT && (c->fp16_prescale_log2 < -24 || c->fp16_prescale_log2 > 24))
-        return fail(COBALT_EINVAL, "fp16_prescale_log2 must lie in [-24, 24]");
+    if (c->x_mode == COBALT_X_FP16_SPLIT) {
+        if (c->fp16_prescale_log2 < -24 || c->fp16_prescale_log2 > 24)
+            return fail(COBALT_EINVAL, "fp16_prescale_log2 must lie in [-24, 24]");
+        const int kmax = fp16_prescale_limit(c);
+        if (kmax != INT32_MIN && c->fp16_prescale_log2 > kmax)
+            return fail(COBALT_EOVERFLOW,
+                        "fp16_prescale_log2 = %d lets full-scale %s samples overflow FP16 with these taps and this "
+                        "bandpass; the largest safe value is %d",
+                        c->fp16_prescale_log2, c->sample_type == COBALT_CI8 ? "8-bit" : "16-bit", kmax);
+    }
 
     s.sample_bytes = c->sample_type == COBALT_CI8 ? 2 : c->sample_type == COBALT_CI16 ? 4 : 8;
     {
@@ -334,6 +368,22 @@ int cobalt_estimate_bytes(const cobalt_config* cfg, size_t* device_bytes) {
     int rc = validate(cfg, &z);
     if (rc != COBALT_OK) return rc;
     *device_bytes = (size_t)z.workspace_bytes;
+    return COBALT_OK;
+}
+
+int cobalt_fp16_prescale_max(const cobalt_config* cfg, int32_t* k_max) {
+    g_last_error.clear();
+    if (!k_max) return fail(COBALT_EINVAL, "k_max is NULL");
+    if (!cfg) return fail(COBALT_EINVAL, "cfg is NULL");
+    cobalt_config c = *cfg;                  // the rest of the setting must be valid
+    c.x_mode = COBALT_X_FP16_SPLIT;
+    c.fp16_prescale_log2 = -24;
+    Sizes z;
+    int rc = validate(&c, &z);
+    if (rc != COBALT_OK) return rc;
+    const int k = fp16_prescale_limit(&c);
+    if (k == INT32_MIN) return fail(COBALT_EINVAL, "float samples have no fixed bound; the caller chooses the prescale");
+    *k_max = k;
     return COBALT_OK;
 }
 

@@ -223,7 +223,8 @@ def workload(name: str, **overrides) -> Workload:
     ``plain_fx``    8 stations, 1 subband, ci16 N(0, 64^2) + tone A=256 at channel 37,
                     zero delays, flat bandpass, FP32 X stage.
     ``int16_share`` 76 stations, 64 subbands, ci16 N(0, 64^2), delays U(+-5 us) with
-                    +-25 ns drift, 5 % bandpass ripple, FP16-split X stage (prescale 2^5).
+                    +-25 ns drift, 5 % bandpass ripple, FP16-split X stage (prescale 2^-1, the
+                    largest for which no 16-bit input overflows FP16 with these taps).
     ``int8_full``   76 stations, 128 subbands, ci8 N(0, 16^2) clipped to +-127, delays and
                     bandpass as int16_share, int8 X stage.
     """
@@ -231,13 +232,60 @@ def workload(name: str, **overrides) -> Workload:
         "plain_fx": dict(S=8, SB=1, sample_type=CI16, x_mode=X_FP32, sigma=64.0, seed=1801,
                          tone_amplitude=256.0, tone_channel=37, f_sb0=150e6),
         "int16_share": dict(S=76, SB=64, sample_type=CI16, x_mode=X_FP16_SPLIT, sigma=64.0, seed=1802,
-                            delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5),
+                            delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1),
         "int8_full": dict(S=76, SB=128, sample_type=CI8, x_mode=X_INT8, sigma=16.0, seed=1803,
                           delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05),
     }
     kw = dict(presets[name])
     kw.update(overrides)
     return Workload(name=name, **kw)
+
+
+def full_scale_streams(fir: np.ndarray, C: int, T: int, n: int, seed: int, sample_type: int = CI16,
+                       tone_channel: int = 37, block: int = 0) -> np.ndarray:
+    """Full-scale test input of four stations [4, 2, 1, n, 2] (storage dtype, one subband):
+
+    * station 0: in every even FIR window (rows wT .. wT+T-1 of C samples, w even) sample
+      t*C + p is ``sgn(h[t*C + p]) * A (1 + i)``, A = the type's largest magnitude (32767 /
+      127); polarisation 1 carries the negated pattern.  The FIR output of the window's last
+      row is then ``A (1 + i) sum_t |h[t*C + p]|`` for every phase p, all in phase, so FFT
+      bin 0 receives ``A (1 + i) sum |h|``: the largest value any input of the type can
+      produce there.  Odd windows hold N(0, (A/32)^2) noise, so no channel is empty.
+    * station 1: a complex tone of amplitude A - 4 sigma_1 centred on ``tone_channel`` over
+      N(0, sigma_1^2) noise (sigma_1 = 256, 8-bit: 4; 42 dB below the tone), clipped to +-A.
+    * station 2: +-A per component with random signs (full-scale white noise).
+    * station 3: N(0, sigma^2) noise plus a tone of amplitude A/16 on ``tone_channel``
+      (strong narrowband interference on ordinary noise).
+    The windows are aligned to the block start; ``block`` keys the random draws.
+    """
+    h = np.asarray(fir, np.float32)
+    A = 127 if sample_type == CI8 else 32767
+    sig = 4.0 if sample_type == CI8 else 64.0
+    dt = storage_dtype(sample_type)
+    rng = np.random.default_rng([seed, block, 0xF5])
+    out = np.zeros((4, 2, 1, n, 2), np.float64)
+    sgn = np.sign(h.astype(np.float64)).reshape(T, C)
+    sgn[sgn == 0] = 1.0
+    rows = n // C
+    even = ((np.arange(rows) // T) % 2 == 0)[:, None]
+    for p, sign in ((0, 1.0), (1, -1.0)):
+        pat = np.tile(sgn, ((rows + T - 1) // T, 1))[:rows] * (sign * A)
+        noise = np.clip(np.rint(rng.standard_normal((rows, C, 2)) * (A / 32)), -A, A)
+        for comp in range(2):
+            out[0, p, 0, :rows * C, comp] = np.where(even, pat, noise[..., comp]).reshape(-1)
+    f0 = (tone_channel - C // 2) / C
+    idx = np.arange(n, dtype=np.float64) + block * n
+    for p in range(2):
+        ph = 2 * np.pi * (f0 * idx + 0.25 * p)
+        sig1 = 4.0 if sample_type == CI8 else 256.0
+        nz = rng.standard_normal((n, 2)) * sig1
+        out[1, p, 0, :, 0] = np.clip(np.rint((A - 4 * sig1) * np.cos(ph) + nz[:, 0]), -A, A)
+        out[1, p, 0, :, 1] = np.clip(np.rint((A - 4 * sig1) * np.sin(ph) + nz[:, 1]), -A, A)
+        out[2, p, 0] = A * rng.choice(np.array([-1.0, 1.0]), size=(n, 2))
+        noise = np.rint(rng.standard_normal((n, 2)) * sig)
+        out[3, p, 0, :, 0] = np.clip(noise[:, 0] + np.rint(A / 16 * np.cos(ph + 1.0)), -A, A)
+        out[3, p, 0, :, 1] = np.clip(noise[:, 1] + np.rint(A / 16 * np.sin(ph + 1.0)), -A, A)
+    return out.astype(dt)
 
 
 def int8_channelised(seed: int, n_chan: int, M: int, n_c: int, pitch: int, extreme: bool = False) -> np.ndarray:

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "cobalt.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(cobalt_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(cobalt_[a-z0-9_]+)\s*\(", txt)))
 
 
 def _lib():
@@ -40,7 +40,7 @@ def _kw(**over):
     w = synth.workload("int16_share")
     kw = dict(n_stations=w.S, n_subbands=w.SB, samples_per_block=w.N, sample_type=w.sample_type,
               x_mode=w.x_mode, fir=w.fir(), subband_freqs=w.subband_freqs(), bandpass=w.bandpass(),
-              fp16_prescale_log2=5, requant_gain=8.0)
+              fp16_prescale_log2=-1, requant_gain=8.0)
     kw.update(over)
     return kw
 
@@ -134,3 +134,4 @@ def test_copies_reject_bad_arguments_before_touching_a_gpu(ptrs, nbytes):
     lib = _lib()
     d0, d1, s = (ct.c_void_p(p) for p in ptrs)
     assert lib.cobalt_device_fanout(d0, d1, s, ct.c_size_t(nbytes), None) == binding.EINVAL
+

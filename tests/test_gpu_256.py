@@ -31,7 +31,7 @@ def _say(msg):
 def _work(S, SB, n_c, st, mode, seed):
     return synth.Workload(name="c256", S=S, SB=SB, sample_type=st, x_mode=mode, N=C * n_c, C=C,
                           sigma=16.0 if st == synth.CI8 else 64.0, seed=seed, delay_spread_s=5e-6,
-                          delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5 if mode == synth.X_FP16_SPLIT else 0)
+                          delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1 if mode == synth.X_FP16_SPLIT else 0)
 
 
 def _oracle_run(w, blocks):

@@ -28,7 +28,7 @@ def _say(msg):
 
 def _work(S, SB, n_c, seed, st=synth.CI16, mode=synth.X_FP16_SPLIT):
     return synth.Workload(name="beam", S=S, SB=SB, sample_type=st, x_mode=mode, N=C * n_c, C=C, sigma=64.0, seed=seed,
-                          delay_spread_s=2e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5)
+                          delay_spread_s=2e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1)
 
 
 def _oracle(w, blocks, dtau, n_stokes, n_int):

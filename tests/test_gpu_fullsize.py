@@ -137,7 +137,7 @@ def test_full_size_beamformer_on_sampled_subbands():
     from oracle import beam as obeam
     w = synth.Workload(name="beam_share", S=48, SB=61, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, C=256,
                        sigma=64.0, seed=1807, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05,
-                       fp16_prescale_log2=5)
+                       fp16_prescale_log2=-1)
     NB, n_int = 127, 16
     sbs = [0, w.SB // 2, w.SB - 1]
     _say(f"CASE fullsize beamformer S={w.S} SB={w.SB} C={w.C} NB={NB} n_int={n_int} subbands={sbs} seed={w.seed}")

@@ -23,7 +23,7 @@ def _say(m):
 def _plan(S, SB, mode=synth.X_FP16_SPLIT, n_c=64):
     from paper_1801_04834_amd import binding
     w = synth.Workload(name="gains", S=S, SB=SB, sample_type=synth.CI16, x_mode=mode, N=64 * n_c,
-                       fp16_prescale_log2=5 if mode == synth.X_FP16_SPLIT else 0)
+                       fp16_prescale_log2=-1 if mode == synth.X_FP16_SPLIT else 0)
     return w, binding.plan_for(w)
 
 

@@ -49,7 +49,7 @@ def _small(name="small", S=3, SB=2, n_c=100, st=synth.CI16, mode=synth.X_FP32, s
     sig = sigma if sigma is not None else (16.0 if st == synth.CI8 else 64.0)
     return synth.Workload(name=name, S=S, SB=SB, sample_type=st, x_mode=mode, N=64 * n_c, sigma=sig, seed=seed,
                           delay_spread_s=kw.pop("spread", 5e-6), delay_drift_s=kw.pop("drift", 25e-9),
-                          ripple=kw.pop("ripple", 0.05), fp16_prescale_log2=5 if mode == synth.X_FP16_SPLIT else 0,
+                          ripple=kw.pop("ripple", 0.05), fp16_prescale_log2=-1 if mode == synth.X_FP16_SPLIT else 0,
                           **kw)
 
 
@@ -174,7 +174,7 @@ def test_x_int8_overflow_bound_extremes():
 def test_x_fp16_split_matches_oracle(S, n_c):
     _say(f"CASE x_fp16 S={S} n_c={n_c}")
     b = _binding()
-    k = 5
+    k = -1  # the plan's prescale (the largest safe one for 16-bit input with these taps)
     w = _small(S=S, SB=1, n_c=n_c, st=synth.CI16, mode=synth.X_FP16_SPLIT)
     with b.plan_for(w) as plan:
         Z = synth.float_channelised(seed=S + n_c, n_chan=64, M=2 * S, n_c=n_c, sigma=7.7)

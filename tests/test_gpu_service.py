@@ -21,7 +21,7 @@ def _workloads():
     n = 64 * 256
     return [
         synth.Workload(name="obsA", S=4, SB=2, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, N=n, seed=1805,
-                       delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=5),
+                       delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1),
         synth.Workload(name="obsB", S=6, SB=1, sample_type=synth.CI8, x_mode=synth.X_INT8, N=n, sigma=16.0,
                        seed=1806, delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05),
         synth.Workload(name="obsC", S=3, SB=3, sample_type=synth.CI16, x_mode=synth.X_FP32, N=n, seed=1807,
