@@ -290,53 +290,88 @@ int cobalt_device_fanout(void* d_dst0, void* d_dst1, const void* d_src, size_t b
 int cobalt_mfma_probe(int32_t x_mode, int64_t iterations, int32_t workgroups, float* d_sink, void* stream);
 
 /* ---- streaming service --------------------------------------------------------------
- * ~1 s blocks from several concurrent observations.  Observations are admitted against an
- * HBM budget; blocks wait in a bounded FIFO per observation and run on the first free stream
- * slot, so blocks of different observations overlap on the device.  Blocks of one observation
- * run in arrival order (the FIR history carries over).  A full FIFO drops the new block
- * (COBALT_EBUSY) instead of stalling the producer, as the paper's pipeline drops data rather
- * than wait (sec. 7.2).  Latency = submit -> the block's visibilities are back in host memory. */
+ * ~1 s blocks from several concurrent observations (the paper's correlator serves several
+ * observations at once, each with its own station and subband set, sec. 7.1-7.3).
+ *  - Memory: the service allocates its HBM budget once, as one device arena, and gives each
+ *    observation a contiguous range of it for its working set: the plan workspace
+ *    (cobalt_estimate_bytes), one device input block and one visibility buffer, each rounded
+ *    up to 256 bytes.  Closing an observation returns its range (the paper allocates its
+ *    buffers once and recycles them through pools of free blocks, sec. 7.1).
+ *  - Admission: an observation that fits is admitted at once; one that does not fit yet
+ *    waits, in arrival order, and is admitted as soon as closes free enough of the arena.
+ *    Its blocks may be submitted meanwhile (they queue up to queue_depth).
+ *  - Continuous batching: n_slots worker threads, each with its own stream, take the next
+ *    queued block of any admitted observation that has no block running, so blocks of
+ *    different observations overlap on the device; blocks of one observation run in arrival
+ *    order, one at a time (the FIR history carries over).
+ *  - Overload: a full FIFO drops the new block (COBALT_EBUSY) instead of stalling the
+ *    producer, as the paper's pipeline drops data rather than wait (sec. 7.2).
+ *  - Latency = submit -> the block's visibilities are back in host memory.
+ *  - Host calls never hold the service's lock across a HIP call. */
 typedef struct cobalt_service cobalt_service;
 
 typedef struct cobalt_service_stats {
-    int64_t submitted, completed, dropped, late;   /* late: latency > deadline             */
+    int64_t submitted, completed, dropped, late;   /* late: latency > deadline; dropped: full
+                                                      FIFO, or closed before admission     */
     double  p50_latency_s, p99_latency_s, max_latency_s;
-    int64_t hbm_used_bytes, hbm_budget_bytes;
+    int64_t hbm_used_bytes, hbm_budget_bytes;      /* arena ranges held / arena size       */
+    int64_t obs_admitted, obs_pending;             /* open observations by state           */
 } cobalt_service_stats;
 
-/* Service on the current device with `n_slots` streams (1..64), per-observation FIFOs of
- * `queue_depth` blocks and a latency deadline (s).  Starts one dispatcher thread.
- * Errors: EINVAL, ENOMEM, EDEVICE. */
+#define COBALT_OBS_PENDING   0   /* waiting for enough of the arena to be free             */
+#define COBALT_OBS_ADMITTED  1
+#define COBALT_OBS_CLOSED    2
+#define COBALT_OBS_FAILED    3   /* admission failed (its plan could not be created)       */
+
+/* Service on the current device: allocates the budget (rounded down to 256 bytes) as one
+ * arena, creates `n_slots` streams (1..64) and as many worker threads; per-observation FIFOs
+ * of `queue_depth` blocks; latency deadline in seconds.  Errors: EINVAL, ENOMEM (the arena),
+ * EDEVICE. */
 int cobalt_service_create(size_t hbm_budget_bytes, int n_slots, int queue_depth, double deadline_s,
                           cobalt_service** out);
 
-/* Admit an observation: its plan workspace plus one device input block and one visibility
- * buffer must fit in the remaining budget, else COBALT_ENOMEM and nothing is allocated.
- * *obs_id identifies it in later calls.  Errors: EINVAL, EUNSUPPORTED, EOVERFLOW (as
- * cobalt_plan_create), ENOMEM, EDEVICE. */
+/* Open an observation with setting cfg (host tables copied).  COBALT_OK: *obs_id identifies
+ * it and it is either admitted or waiting for admission (cobalt_service_query tells which).
+ * Errors: EINVAL, EUNSUPPORTED, EOVERFLOW (as cobalt_plan_create); ENOMEM when its working
+ * set exceeds the whole budget (nothing is allocated); EDEVICE or ENOMEM when its plan could
+ * not be created in an arena range that was free. */
 int cobalt_service_open(cobalt_service* svc, const cobalt_config* cfg, int* obs_id);
 
-/* Queue one block: h_block host input ([S][P][SB][N] samples; pinned memory lets the copy run
- * asynchronously), h_delays [S][2] (copied), h_vis host output (visibility layout).  Both host
- * buffers must stay valid until cobalt_service_wait returns for *ticket.  A full FIFO drops the
- * block: COBALT_EBUSY with *ticket = -1.  Errors: EINVAL, EBUSY. */
+/* *state = COBALT_OBS_PENDING / ADMITTED / CLOSED / FAILED (for FAILED,
+ * cobalt_service_last_error() gives the reason).  Errors: EINVAL. */
+int cobalt_service_query(cobalt_service* svc, int obs_id, int* state);
+
+/* Queue one block: h_block host input ([S][P][SB][N] samples of the setting's type, S*2*SB*N
+ * samples; pinned memory lets the copy run asynchronously), h_delays [S][2] (copied), h_vis
+ * host output ([SB][C][B][4] complex visibilities, SB*C*B*32 bytes).  The library cannot
+ * check the host buffers' sizes: they must hold at least these many bytes and stay valid
+ * until cobalt_service_wait returns for *ticket.  A full FIFO drops the block: COBALT_EBUSY
+ * with *ticket = -1.  Errors: EINVAL (unknown or closed observation), EBUSY, EDEVICE (the
+ * observation's admission failed). */
 int cobalt_service_submit(cobalt_service* svc, int obs_id, const void* h_block, const double* h_delays,
                           void* h_vis, int64_t* ticket);
 
 /* Block until `ticket` has completed; *latency_s (may be NULL) = submit -> completion.  Each
- * ticket can be waited once.  Errors: EINVAL, EDEVICE (an asynchronous device error). */
+ * ticket can be waited once.  Returns the block's own result: COBALT_OK, EBUSY (dropped
+ * because its observation was closed before admission), EDEVICE (a device error while it
+ * ran), or EINVAL (unknown ticket). */
 int cobalt_service_wait(cobalt_service* svc, int64_t ticket, double* latency_s);
 
-/* Stop (1) or resume (0) dispatching; queued blocks stay queued (tests force full FIFOs). */
+/* Stop (1) or resume (0) dispatching blocks; queued blocks stay queued (tests force full
+ * FIFOs).  Admission continues while paused. */
 int cobalt_service_pause(cobalt_service* svc, int paused);
 
 /* Counters and latency percentiles over all completed blocks. */
 int cobalt_service_get_stats(cobalt_service* svc, cobalt_service_stats* out);
 
-/* Finish the observation's queued blocks, then free its plan and buffers (budget returns). */
+/* Finish the observation's queued blocks (an observation still waiting for admission drops
+ * them instead), then free its plan and return its arena range; waiting observations that
+ * now fit are admitted. */
 int cobalt_service_close(cobalt_service* svc, int obs_id);
 
-/* Finish all queued blocks, stop the dispatcher and free everything.  NULL is a no-op. */
+/* Finish all queued blocks of admitted observations (blocks of observations still waiting
+ * for admission are dropped), stop the workers and free everything.  Every cobalt_service_wait
+ * must have returned first.  NULL is a no-op. */
 int cobalt_service_destroy(cobalt_service* svc);
 
 /* Message for the last service error on this host thread. */

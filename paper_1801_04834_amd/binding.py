@@ -26,7 +26,8 @@ EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_fp16_prescale
             "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
             "cobalt_beamform_channelized", "cobalt_correlate_channelized", "cobalt_reset_history",
             "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_device_fanout", "cobalt_mfma_probe", "cobalt_plan_destroy",
-            "cobalt_last_error", "cobalt_service_create", "cobalt_service_open", "cobalt_service_submit",
+            "cobalt_last_error", "cobalt_service_create", "cobalt_service_open", "cobalt_service_query",
+            "cobalt_service_submit",
             "cobalt_service_wait", "cobalt_service_pause", "cobalt_service_get_stats", "cobalt_service_close",
             "cobalt_service_destroy", "cobalt_service_last_error"]
 
@@ -70,7 +71,11 @@ class BeamParams(ct.Structure):
 class ServiceStats(ct.Structure):
     _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("dropped", ct.c_int64),
                 ("late", ct.c_int64), ("p50_latency_s", ct.c_double), ("p99_latency_s", ct.c_double),
-                ("max_latency_s", ct.c_double), ("hbm_used_bytes", ct.c_int64), ("hbm_budget_bytes", ct.c_int64)]
+                ("max_latency_s", ct.c_double), ("hbm_used_bytes", ct.c_int64), ("hbm_budget_bytes", ct.c_int64),
+                ("obs_admitted", ct.c_int64), ("obs_pending", ct.c_int64)]
+
+
+OBS_PENDING, OBS_ADMITTED, OBS_CLOSED, OBS_FAILED = 0, 1, 2, 3
 
 
 _LIB = None
@@ -107,6 +112,7 @@ def load_library():
     lib.cobalt_last_error.restype = ct.c_char_p
     lib.cobalt_service_create.argtypes = [ct.c_size_t, i32, i32, ct.c_double, ct.POINTER(vp)]
     lib.cobalt_service_open.argtypes = [vp, ct.POINTER(Config), ct.POINTER(i32)]
+    lib.cobalt_service_query.argtypes = [vp, i32, ct.POINTER(i32)]
     lib.cobalt_service_submit.argtypes = [vp, i32, vp, ct.POINTER(ct.c_double), vp, ct.POINTER(ct.c_int64)]
     lib.cobalt_service_wait.argtypes = [vp, ct.c_int64, ct.POINTER(ct.c_double)]
     lib.cobalt_service_pause.argtypes = [vp, i32]
@@ -482,22 +488,28 @@ def _scheck(rc):
         raise CobaltError(rc, msg)
 
 
-def _host_ptr(a):
-    """Data pointer of a contiguous host numpy array or CPU torch tensor."""
+def _host_buffer(a, nbytes, name):
+    """Data pointer of a contiguous host buffer (numpy array or CPU torch tensor) holding
+    exactly ``nbytes`` bytes."""
     if isinstance(a, np.ndarray):
         if not a.flags.c_contiguous:
-            raise ValueError("host buffer must be contiguous")
+            raise ValueError(f"{name}: host buffer must be contiguous")
+        if a.nbytes != nbytes:
+            raise ValueError(f"{name}: need {nbytes} bytes, got {a.nbytes}")
         return ct.c_void_p(a.ctypes.data)
     if a.is_cuda or not a.is_contiguous():
-        raise ValueError("host buffer must be a contiguous CPU tensor")
+        raise ValueError(f"{name}: host buffer must be a contiguous CPU tensor")
+    if a.numel() * a.element_size() != nbytes:
+        raise ValueError(f"{name}: need {nbytes} bytes, got {a.numel() * a.element_size()}")
     return ct.c_void_p(a.data_ptr())
 
 
 class Service:
-    """Streaming service (``cobalt_service``): observations admitted by HBM budget, blocks
-    dispatched to free stream slots as they arrive.  Host buffers passed to ``submit`` are
-    kept referenced until ``wait`` returns for their ticket (use pinned tensors for
-    asynchronous copies)."""
+    """Streaming service (``cobalt_service``): the HBM budget is allocated once as an arena;
+    observations are admitted when their working set fits (else they wait, in arrival order,
+    until closes free enough of it); blocks run on free worker streams as they arrive.  Host
+    buffers passed to ``submit`` are kept referenced until ``wait`` returns for their ticket
+    (use pinned tensors for asynchronous copies)."""
 
     def __init__(self, hbm_budget_bytes, n_slots=4, queue_depth=4, deadline_s=196608 / 195312.5):
         import torch
@@ -510,17 +522,26 @@ class Service:
         self._held = {}
 
     def open(self, **kw):
-        """Admit an observation (keywords as ``Plan``); returns its id.  Raises CobaltError
-        with code ENOMEM when the HBM budget cannot hold it."""
+        """Open an observation (keywords as ``Plan``); returns its id.  It is admitted at once
+        when its working set fits, else it waits for admission (``state``).  Raises
+        CobaltError with code ENOMEM when it exceeds the whole budget."""
         cfg, keep = make_config(**kw)
         oid = ct.c_int(-1)
         _scheck(self._lib.cobalt_service_open(self._ptr, ct.byref(cfg), ct.byref(oid)))
-        S, SB = kw["n_stations"], kw["n_subbands"]
+        S, SB, C = kw["n_stations"], kw["n_subbands"], kw.get("n_channels", 64)
         B = S * (S + 1) // 2
         vis_dtype = np.int32 if kw["x_mode"] == X_INT8 else np.float32
-        self._obs[oid.value] = dict(kw=kw, keep=keep, S=S, vis_shape=(SB, kw.get("n_channels", 64), B, 4, 2),
-                                    vis_dtype=vis_dtype)
+        sample_b = {CI8: 2, CI16: 4, CF32: 8}[kw["sample_type"]]
+        self._obs[oid.value] = dict(kw=kw, keep=keep, S=S, vis_shape=(SB, C, B, 4, 2), vis_dtype=vis_dtype,
+                                    in_bytes=S * 2 * SB * kw["samples_per_block"] * sample_b,
+                                    vis_bytes=SB * C * B * 4 * 8)
         return oid.value
+
+    def state(self, obs_id):
+        """OBS_PENDING, OBS_ADMITTED, OBS_CLOSED or OBS_FAILED."""
+        st = ct.c_int(-1)
+        _scheck(self._lib.cobalt_service_query(self._ptr, int(obs_id), ct.byref(st)))
+        return st.value
 
     def vis_buffer(self, obs_id, pinned=True):
         """A host buffer for one block's visibilities of this observation."""
@@ -530,13 +551,20 @@ class Service:
         return torch.empty(o["vis_shape"], dtype=dt, pin_memory=pinned)
 
     def submit(self, obs_id, h_block, delays, h_vis):
-        """Queue one block; returns its ticket, or None when the FIFO was full (dropped)."""
+        """Queue one block; returns its ticket, or None when the FIFO was full (dropped).
+        ``h_block`` must hold exactly one input block of the observation and ``h_vis`` one
+        visibility block (contiguous host memory)."""
+        o = self._obs.get(obs_id)
+        if o is None:
+            raise ValueError(f"unknown observation {obs_id}")
         d = np.ascontiguousarray(delays, np.float64).reshape(-1)
-        if d.size != 2 * self._obs[obs_id]["S"]:
+        if d.size != 2 * o["S"]:
             raise ValueError("delays: need S x 2 float64 seconds")
+        pin = _host_buffer(h_block, o["in_bytes"], "h_block")
+        pvis = _host_buffer(h_vis, o["vis_bytes"], "h_vis")
         t = ct.c_int64(-1)
-        rc = self._lib.cobalt_service_submit(self._ptr, int(obs_id), _host_ptr(h_block),
-                                             d.ctypes.data_as(ct.POINTER(ct.c_double)), _host_ptr(h_vis), ct.byref(t))
+        rc = self._lib.cobalt_service_submit(self._ptr, int(obs_id), pin, d.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                             pvis, ct.byref(t))
         if rc == EBUSY:
             return None
         _scheck(rc)

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/cobalt.h"
+
 namespace cobalt {
 
 // Built instantiations: C = 64 channels (the correlator setting) and C = 256 (the paper's
@@ -87,5 +89,11 @@ hipError_t launch_device_fanout(void* dst0, void* dst1, const void* src, int64_t
 hipError_t launch_apply_gains(const void* vis0, const void* gains, void* vis, int n_chan, int S, hipStream_t st);
 hipError_t launch_apply_gains_adjoint(const void* vis0, const void* gains, const void* grad_vis, void* grad_gains, int n_chan,
                                       int S, hipStream_t st);
+
+// cobalt_plan_create with the device workspace given by the caller (d_workspace: 256-byte
+// aligned, cobalt_estimate_bytes() bytes, left allocated by cobalt_plan_destroy) or, for
+// NULL, allocated by the plan.  Used by the streaming service, which carves observation
+// workspaces out of one arena allocated at its creation.
+int plan_create_impl(const cobalt_config* cfg, void* d_workspace, cobalt_plan** out);
 
 }  // namespace cobalt

@@ -167,6 +167,7 @@ struct cobalt_plan {
     Sizes z;
     int device = 0;
     char* d_ws = nullptr;        // one allocation for the whole workspace
+    bool owns_ws = true;         // false: the workspace belongs to the caller (service arena)
     void* d_chan = nullptr;
     void* d_hist[2] = {nullptr, nullptr};
     int hist_cur = 0;
@@ -213,7 +214,7 @@ void free_plan(cobalt_plan* p) {
         if (p->ring_ev[i]) (void)hipEventDestroy(p->ring_ev[i]);
     if (p->done_ev) (void)hipEventDestroy(p->done_ev);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
-    if (p->d_ws) (void)hipFree(p->d_ws);
+    if (p->d_ws && p->owns_ws) (void)hipFree(p->d_ws);
     delete p;
 }
 
@@ -387,13 +388,20 @@ int cobalt_fp16_prescale_max(const cobalt_config* cfg, int32_t* k_max) {
     return COBALT_OK;
 }
 
-int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) {
+}  // extern "C"
+
+// Plan creation with the workspace either allocated here or given by the caller (the
+// streaming service carves observation workspaces out of one device arena).  The tables
+// and the zeroed history are uploaded on a private stream that is synchronised before
+// return, so creating a plan does not wait for work other plans have queued on the device.
+int cobalt::plan_create_impl(const cobalt_config* cfg, void* d_workspace, cobalt_plan** out) {
     g_last_error.clear();
     if (!out) return fail(COBALT_EINVAL, "out is NULL");
     *out = nullptr;
     Sizes z;
     int rc = validate(cfg, &z);
     if (rc != COBALT_OK) return rc;
+    if (d_workspace && (uintptr_t)d_workspace % 256) return fail(COBALT_EINVAL, "workspace must be 256-byte aligned");
 
     cobalt_plan* p = new (std::nothrow) cobalt_plan();
     if (!p) return fail(COBALT_ENOMEM, "host allocation failed");
@@ -405,11 +413,17 @@ int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) {
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
 
-    e = hipMalloc((void**)&p->d_ws, (size_t)z.workspace_bytes);
-    if (e != hipSuccess) {
-        free_plan(p);
-        (void)hipGetLastError();
-        return fail(COBALT_ENOMEM, "hipMalloc(%lld bytes) failed: %s", (long long)z.workspace_bytes, hipGetErrorString(e));
+    if (d_workspace) {
+        p->d_ws = (char*)d_workspace;
+        p->owns_ws = false;
+    } else {
+        e = hipMalloc((void**)&p->d_ws, (size_t)z.workspace_bytes);
+        if (e != hipSuccess) {
+            p->d_ws = nullptr;
+            free_plan(p);
+            (void)hipGetLastError();
+            return fail(COBALT_ENOMEM, "hipMalloc(%lld bytes) failed: %s", (long long)z.workspace_bytes, hipGetErrorString(e));
+        }
     }
     char* q = p->d_ws;
     p->d_chan = q;                q += round_up(z.chan_bytes, 256);
@@ -438,17 +452,26 @@ int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) {
                               : cfg->x_mode == COBALT_X_INT8   ? (double)cfg->requant_gain
                                                                : 1.0;
     for (int c = 0; c < z.C; ++c) bscale[c] = (float)((cfg->h_bandpass ? (double)cfg->h_bandpass[c] : 1.0) * mode_scale);
-    e = hipMemcpy(p->d_fir, cfg->h_fir, sizeof(float) * kT * z.C, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_bscale, bscale, sizeof(float) * z.C, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_fsb, cfg->h_subband_freq_hz, sizeof(double) * z.SB, hipMemcpyHostToDevice);
-    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "table upload"); }
+    hipStream_t init = nullptr;
+    e = hipStreamCreateWithFlags(&init, hipStreamNonBlocking);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipStreamCreate"); }
+    e = hipMemcpyAsync(p->d_fir, cfg->h_fir, sizeof(float) * kT * z.C, hipMemcpyHostToDevice, init);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_bscale, bscale, sizeof(float) * z.C, hipMemcpyHostToDevice, init);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_fsb, cfg->h_subband_freq_hz, sizeof(double) * z.SB, hipMemcpyHostToDevice, init);
     // FIR history starts at zero (no samples before the first block), its rows unflagged
-    e = launch_zero_fill(p->d_hist[0], round_up(z.hist_bytes, 256) * 2 + round_up(z.rowhist_bytes, 256) * 2, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "history init"); }
+    if (e == hipSuccess)
+        e = launch_zero_fill(p->d_hist[0], round_up(z.hist_bytes, 256) * 2 + round_up(z.rowhist_bytes, 256) * 2, init);
+    const hipError_t es = hipStreamSynchronize(init);   // the host tables may be freed after return
+    if (e == hipSuccess) e = es;
+    (void)hipStreamDestroy(init);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "table upload / history init"); }
     *out = p;
     return COBALT_OK;
 }
+
+extern "C" {
+
+int cobalt_plan_create(const cobalt_config* cfg, cobalt_plan** out) { return plan_create_impl(cfg, nullptr, out); }
 
 int cobalt_plan_query(const cobalt_plan* p, cobalt_plan_info* info) {
     g_last_error.clear();
