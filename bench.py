@@ -87,10 +87,13 @@ def parse():
     ap.add_argument("--gains-steps", type=int, default=3,
                     help="steps of the differentiable gain-applied correlator (48 stations, 16 subbands; 0: skip)")
     ap.add_argument("--service", action="store_true",
-                    help="streaming service run instead: three concurrent observations (24/48/76 stations, "
+                    help="only the streaming service leg: three concurrent observations (24/48/76 stations, "
                          "32/64/128 subbands, ci16/ci16/ci8), Poisson block arrivals, HBM-budget admission")
-    ap.add_argument("--service-seconds", type=float, default=20.0)
+    ap.add_argument("--service-seconds", type=float, default=15.0,
+                    help="length of the streaming service leg of the default run (0: skip)")
     ap.add_argument("--service-budget-gib", type=float, default=48.0)
+    ap.add_argument("--int8-steps", type=int, default=20,
+                    help="steps of the 8-bit mode leg (76 stations, 128 subbands, int8 X stage; 0: skip)")
     ap.add_argument("--mfma-probe-iters", type=int, default=16384,
                     help="rounds of the dense MFMA probe (FP16 and int8, 512 workgroups), run first: the MFMA rate "
                          "this GPU sustains under that load, reported as mfma_probe (0: skip)")
@@ -265,6 +268,59 @@ def time_gains(torch, binding, synth, steps, device):
     return w, n_ent, fwd, adj
 
 
+def int8_leg(args, torch, binding, synth, dev, probe):
+    """The 8-bit mode workload: 76 stations x 2 pol, 128 subbands of ci8 samples, int8 X stage
+    (int8 MFMA, int32 sums), F then X per step as in the main leg, the streaming schedule, and
+    the block latency over 60 blocks.  Rooflines: X against the dense int8 MFMA peak; F against
+    the non-packed FP32 vector rate (4 B per sample: bound by arithmetic), with its GB/s."""
+    w = synth.workload("int8_full")
+    log(f"bench: 8-bit leg {w.S} stations x {w.SB} subbands; generating input")
+    x = make_input(w, torch, dev)
+    delays = w.delays(0)
+    plan = binding.plan_for(w)
+    cmacs = plan.info["useful_cmacs"]
+    block_s = w.N / synth.SAMPLE_RATE_HZ
+    wall, f_ms, x_ms, vis = time_steps(torch, plan, x, delays, args.steps, args.warmup)
+    del vis
+    step_ms = wall * 1e3
+    if not args.no_pipeline:
+        step_ms = time_pipelined(torch, plan, x, delays, args.steps, args.warmup) * 1e3
+    lat = block_latency(torch, plan, x, delays, max(args.steps, 60))
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+    samples = w.M * w.SB * w.N
+    f_s, x_s = float(np.mean(f_ms)) * 1e-3, float(np.mean(x_ms)) * 1e-3
+    f_tf = samples * F_FLOP_PER_SAMPLE / f_s / 1e12
+    x_tops = cmacs * 8 / x_s / 1e12
+    f_kernel = f"fstage_kernel<{w.sample_type}, {w.x_mode}, {w.C}>"
+    x_kernel = f"xstage_mfma_kernel<{w.x_mode}, {(w.M + 31) // 32}>"
+    out = {
+        "workload": f"int8_full: {w.S} stations x 2 pol, {w.SB} subbands, ci8 N(0, 16^2) clipped to +-127, "
+                    f"16-tap PPF -> 64 ch, N={w.N}; int8 MFMA X stage with int32 sums",
+        "value": round(cmacs / (step_ms * 1e-3) / 1e12, 4), "unit": "TeraMAC/s",
+        "ms_per_step": round(step_ms, 4), "ms_per_step_serial": round(wall * 1e3, 4),
+        "real_time_factor": round(block_s / (step_ms * 1e-3), 2),
+        "block_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                             "p99": round(float(np.percentile(lat, 99)), 3), "n": int(lat.size),
+                             "deadline_ms": round(block_s * 1e3, 3)},
+        "x_stage_tmacs": round(cmacs / x_s / 1e12, 3),
+        "roofline_x": {"bound": "mfma", "achieved": round(x_tops, 1), "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
+                       "frac": round(x_tops / INT8_MFMA_PEAK_TOPS, 4), "traffic": measured_traffic(x_kernel),
+                       "kernel": x_kernel, "ms": round(x_s * 1e3, 4),
+                       "operand_gbs": round(w.SB * w.C * w.M * w.n_c * 2 / x_s / 1e9, 1)},
+        "roofline_f": {"bound": "alu", "achieved": round(f_tf, 1), "peak": FP32_VALU_NOPACK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(f_tf / FP32_VALU_NOPACK_TFLOPS, 4), "traffic": measured_traffic(f_kernel),
+                       "kernel": f_kernel, "ms": round(f_s * 1e3, 4),
+                       "hbm_gbs": round(samples * 4 / f_s / 1e9, 1)},
+    }
+    if probe is not None:
+        out["roofline_x"]["of_mfma_probe"] = round(x_tops / probe["int8_tops"], 4)
+    log(f"bench: 8-bit leg F {f_s * 1e3:.3f} ms, X {x_s * 1e3:.3f} ms, step {step_ms:.3f} ms "
+        f"({out['value']} TeraMAC/s), latency p99 {out['block_latency_ms']['p99']} ms")
+    return out
+
+
 def block_latency(torch, plan, x, delays, n):
     """Submit one block, wait for it; host-side enqueue-to-completion time (ms)."""
     vis = plan.empty_vis()
@@ -303,19 +359,27 @@ def cpu_baseline(w, n_sub):
             "seconds": dt}
 
 
-def service_main(args, torch, binding, synth):
-    """Streaming service: each observation produces one ~1 s block per Poisson arrival (mean
-    inter-arrival = block duration); blocks are submitted from host (pinned) memory and
-    their visibilities copied back.  Reports latency percentiles against the block deadline,
-    drops, late blocks and the sustained real-time factor per observation."""
+def service_workloads(synth):
+    """The three concurrent observations of the streaming-service workload."""
+    kw = dict(delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05)
+    return [synth.Workload(name="O1", S=24, SB=32, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1805,
+                           fp16_prescale_log2=-1, **kw),
+            synth.Workload(name="O2", S=48, SB=64, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1806,
+                           fp16_prescale_log2=-1, **kw),
+            synth.Workload(name="O3", S=76, SB=128, sample_type=synth.CI8, x_mode=synth.X_INT8, sigma=16.0, seed=1807,
+                           **kw)]
+
+
+def service_leg(args, torch, binding, synth):
+    """Streaming service: three concurrent observations (24 st x 32 SB ci16, 48 st x 64 SB ci16,
+    76 st x 128 SB ci8), each producing one ~1 s block per Poisson arrival (mean inter-arrival =
+    the block duration) for ``service_seconds``; blocks are submitted from pinned host memory
+    and their visibilities copied back (latency includes both copies).  Returns latency
+    percentiles (all blocks and per observation) against the block deadline, drops, late
+    blocks and the sustained real-time factor (seconds of data correlated per wall second)."""
     import threading
     block_s = synth.BLOCK_SAMPLES / synth.SAMPLE_RATE_HZ
-    ws = [synth.Workload(name="O1", S=24, SB=32, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1805,
-                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1),
-          synth.Workload(name="O2", S=48, SB=64, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, seed=1806,
-                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05, fp16_prescale_log2=-1),
-          synth.Workload(name="O3", S=76, SB=128, sample_type=synth.CI8, x_mode=synth.X_INT8, sigma=16.0, seed=1807,
-                         delay_spread_s=5e-6, delay_drift_s=25e-9, ripple=0.05)]
+    ws = service_workloads(synth)
     t0 = time.perf_counter()
     host = []
     for w in ws:
@@ -325,13 +389,14 @@ def service_main(args, torch, binding, synth):
             blk[:, :, sb0:sb0 + len(sbs)].copy_(torch.from_numpy(w.block(0, subbands=sbs)))
         host.append(blk)
     log(f"bench: service inputs generated ({time.perf_counter() - t0:.1f} s)")
-    svc = binding.Service(int(args.service_budget_gib * 2**30), n_slots=3, queue_depth=4, deadline_s=block_s)
+    budget = int(args.service_budget_gib * 2**30)
+    svc = binding.Service(budget, n_slots=3, queue_depth=4, deadline_s=block_s)
     oids = [svc.open(**binding.plan_kwargs(w)) for w in ws]
+    admitted = [svc.state(o) == binding.OBS_ADMITTED for o in oids]
     outs = [[svc.vis_buffer(o) for _ in range(4)] for o in oids]
-    # warm-up: one block per observation
-    for i, w in enumerate(ws):
+    for i, w in enumerate(ws):                       # warm-up: one block per observation
         svc.wait(svc.submit(oids[i], host[i], w.delays(0), outs[i][0]))
-    warm_stats = svc.stats()
+    warm = svc.stats()
     rng = np.random.default_rng(1805)
     arrivals = []
     for i in range(len(ws)):
@@ -341,63 +406,77 @@ def service_main(args, torch, binding, synth):
             t += rng.exponential(block_s)
             k += 1
     arrivals.sort()
-    pending = [[] for _ in ws]
-    lock = threading.Lock()
-    done = {"n": 0}
+    queues = [[] for _ in ws]
+    lats = [[] for _ in ws]
+    cv = threading.Condition()
+    state = {"stop": False}
 
     def waiter(i):
         while True:
-            with lock:
-                item = pending[i].pop(0) if pending[i] else None
-            if item is None:
-                if done.get("stop"):
+            with cv:
+                while not queues[i] and not state["stop"]:
+                    cv.wait()
+                if not queues[i]:
                     return
-                time.sleep(0.001)
-                continue
-            if item >= 0:
-                svc.wait(item)
-                with lock:
-                    done["n"] += 1
+                tk = queues[i].pop(0)
+            lats[i].append(svc.wait(tk))
 
     ths = [threading.Thread(target=waiter, args=(i,)) for i in range(len(ws))]
     for th in ths:
         th.start()
     start = time.perf_counter()
     submitted = [0] * len(ws)
+    dropped = [0] * len(ws)
     for t, i, k in arrivals:
         dt = start + t - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
         tk = svc.submit(oids[i], host[i], ws[i].delays(k), outs[i][k % 4])
         submitted[i] += 1
-        with lock:
-            pending[i].append(tk if tk is not None else -1)
-    while True:
-        with lock:
-            if all(not p for p in pending):
-                break
-        time.sleep(0.01)
-    done["stop"] = True
+        if tk is None:
+            dropped[i] += 1
+            continue
+        with cv:
+            queues[i].append(tk)
+            cv.notify_all()
+    with cv:
+        state["stop"] = True
+        cv.notify_all()
     for th in ths:
         th.join()
     wall = time.perf_counter() - start
     st = svc.stats()
     svc.destroy()
-    completed = st["completed"] - warm_stats["completed"]
+    del host
+    completed = st["completed"] - warm["completed"]
+    allv = np.array([v for l in lats for v in l]) * 1e3
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3) if len(a) else None  # noqa: E731
+    per_obs = []
+    for i, w in enumerate(ws):
+        a = np.array(lats[i]) * 1e3
+        per_obs.append({"observation": f"{w.name}: {w.S} stations x 2 pol, {w.SB} subbands, "
+                                       f"{'ci8 int8 X' if w.sample_type == synth.CI8 else 'ci16 FP16-split X'}",
+                        "blocks": int(a.size), "dropped": dropped[i], "p50_ms": pct(a, 50), "p99_ms": pct(a, 99),
+                        "max_ms": round(float(a.max()), 3) if a.size else None})
     out = {
-        "metric": METRIC, "mode": "service", "value": round(st["p99_latency_s"] * 1e3, 3), "unit": "ms p99 block latency",
-        "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
-        "config": {"workload": "three concurrent observations: 24 st x 32 SB ci16, 48 st x 64 SB ci16, 76 st x 128 SB ci8; "
-                               "Poisson arrivals, mean inter-arrival = block duration", "budget_gib": args.service_budget_gib,
-                   "seconds": args.service_seconds, "slots": 3},
-        "blocks_submitted": submitted, "blocks_completed": completed, "dropped": st["dropped"], "late": st["late"],
-        "p50_latency_ms": round(st["p50_latency_s"] * 1e3, 3), "p99_latency_ms": round(st["p99_latency_s"] * 1e3, 3),
-        "max_latency_ms": round(st["max_latency_s"] * 1e3, 3), "deadline_ms": round(block_s * 1e3, 3),
-        "sustained_real_time_factor_per_observation": round(completed * block_s / wall / len(ws), 3),
+        "workload": "three concurrent observations: 24 st x 32 SB ci16, 48 st x 64 SB ci16, 76 st x 128 SB ci8; "
+                    "Poisson block arrivals, mean inter-arrival = block duration",
+        "seconds": args.service_seconds, "slots": 3, "budget_gib": args.service_budget_gib,
+        "admitted_at_open": admitted, "blocks_submitted": int(sum(submitted)), "blocks_completed": int(completed),
+        "dropped": int(st["dropped"]), "late": int(st["late"] - warm["late"]),
+        "p50_ms": pct(allv, 50), "p99_ms": pct(allv, 99), "max_ms": round(float(allv.max()), 3) if allv.size else None,
+        "deadline_ms": round(block_s * 1e3, 3),
+        "sustained_real_time_factor": round(completed * block_s / wall, 3),
+        "offered_real_time_factor": round(sum(submitted) * block_s / args.service_seconds, 3),
+        "per_observation": per_obs,
         "hbm_admitted_gib": round(st["hbm_used_bytes"] / 2**30, 2),
-        "note": "latency includes host->device copy of the block and device->host copy of the visibilities",
+        "note": "latency = submit -> visibilities in host memory (host->device and device->host copies included); "
+                "sustained real-time factor = seconds of station data correlated per wall-clock second, summed "
+                "over the observations (3 when all keep up)",
     }
-    print(json.dumps(out), flush=True)
+    log(f"bench: service {completed} blocks in {wall:.1f} s, p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms, "
+        f"dropped {out['dropped']}, late {out['late']}")
+    return out
 
 
 def main():
@@ -416,7 +495,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.service:
-        service_main(args, torch, binding, synth)
+        svc = service_leg(args, torch, binding, synth)
+        print(json.dumps({"metric": METRIC, "mode": "service", "value": svc["p99_ms"], "unit": "ms p99 block latency",
+                          "higher_is_better": False, "n_gpus": 1, "data": "synthetic", "service": svc}), flush=True)
         return
     w = synth.workload(args.workload)
     log(f"bench: workload {w.name} S={w.S} SB={w.SB} N={w.N} mode={w.x_mode}; generating input")
@@ -592,6 +673,18 @@ def main():
         cpu = cpu_baseline(w, args.cpu_subbands)
         log(f"bench: oracle {cpu['seconds']:.2f} s -> {cpu['value']:.5f} TeraMAC/s")
 
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+    int8 = None
+    if args.int8_steps > 0:
+        a8 = argparse.Namespace(**vars(args))
+        a8.steps = args.int8_steps
+        int8 = int8_leg(a8, torch, binding, synth, dev, probe)
+    service = None
+    if args.service_seconds > 0:
+        service = service_leg(args, torch, binding, synth)
+
     value = cmacs / (step_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "TeraMAC/s", "n_gpus": 1,
@@ -623,10 +716,11 @@ def main():
         "coarse_delay_and_flags": flagged,
         "beamformer": beam,
         "differentiable_gains": gains,
+        "int8_mode": int8,
+        "service": service,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

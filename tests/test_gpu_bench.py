@@ -1,6 +1,7 @@
 """The benchmark's output contract on a GPU: one JSON line with the metric, the whole-step
 throughput, the roofline object of the dominant kernel (bound, achieved, peak, unit, frac,
-traffic) and the probes, from a short run of the default workload."""
+traffic), the probes, the 8-bit mode leg and the streaming service leg, from a short run of the
+default workload."""
 
 import json
 import os
@@ -18,7 +19,8 @@ def test_bench_prints_one_json_line_with_roofline():
     print("CASE bench short run", flush=True)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "1", "--fp32-steps", "0",
                         "--flags-steps", "0", "--beam-steps", "0", "--gains-steps", "0", "--no-cpu-baseline",
-                        "--mfma-probe-iters", "256", "--copy-calibration-mib", "256"],
+                        "--mfma-probe-iters", "256", "--copy-calibration-mib", "256", "--int8-steps", "2",
+                        "--service-seconds", "3"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -35,3 +37,12 @@ def test_bench_prints_one_json_line_with_roofline():
     assert roof["bound"] in ("hbm", "mfma", "alu") and 0 < roof["frac"] < 1
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
     assert d["mfma_probe"]["fp16_tflops"] > 0 and d["hbm_copy_gbs"] > 0
+    i8 = d["int8_mode"]
+    assert i8["value"] > 0 and i8["block_latency_ms"]["n"] >= 60
+    for r in (i8["roofline_x"], i8["roofline_f"]):
+        assert 0 < r["frac"] < 1 and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    sv = d["service"]
+    assert sv["blocks_completed"] + sv["dropped"] == sv["blocks_submitted"]
+    assert len(sv["per_observation"]) == 3 and all(sv["admitted_at_open"])
+    if sv["blocks_completed"]:
+        assert 0 < sv["p50_ms"] <= sv["p99_ms"] <= sv["max_ms"]
