@@ -18,7 +18,8 @@
 //   (imaginary part), so it is not multiplied but added from hl at the end (where registers
 //   allow: every diagonal tile of the 152-input grid).
 //   int8: exact int32 sums.
-// Plain FP32 form: 8x8 register blocks of complex FMAs on the VALU.
+// Plain FP32 form: complex FMAs on the VALU over halves of 8x8 blocks of inputs, with partial
+// sums over 128 channel samples folded into running totals.
 #include <type_traits>
 
 #include "cobalt_internal.h"
@@ -352,19 +353,38 @@ hipError_t launch_mode(const XArgs& a, hipStream_t st) {
 
 // ------------------------------------------------------------------ plain FP32 form ---
 constexpr int kF32Kc = 16;        // complex samples per LDS chunk
+// Blocked accumulation: products are summed over kF32Fold channel samples into partial sums,
+// which are then added to the running totals.  A single running sum over all N_c samples
+// leaves a relative rounding error of about u sqrt(N_c) / 6 (u = 2^-24; the additions round
+// at the size of the growing sum); partial sums of b samples folded into the totals leave
+// about u (b / sqrt(N_c) + sqrt(N_c / b)) / 6, smallest near b = sqrt(N_c): 7.7 times less
+// at N_c = 3072 and b = 128.
+constexpr int kF32Fold = 128;
+static_assert(kF32Fold % kF32Kc == 0, "a fold spans whole LDS chunks");
 
-__global__ __launch_bounds__(256) void xstage_fp32_kernel(XArgs a) {
-    extern __shared__ float2 zl[];                 // [kF32Kc][ls] with ls = 8*nb8 + 1
-    const int tid = threadIdx.x;
-    const int groups = (a.n_blocks8 * (a.n_blocks8 + 1) / 2 + 255) / 256;
+// One thread per half (4 rows x 8 columns) of an 8x8 block of inputs in the lower triangle;
+// complex FMAs from an LDS-staged chunk of kF32Kc channel samples.  The half-block keeps the
+// partial sums and the running totals in registers at three waves per SIMD; the kernel
+// stays bound by its FMAs (per chunk step a wave issues 128 FMAs against 12 LDS reads).  A
+// workgroup of up to kF32Threads threads covers a whole channel (every input row staged
+// once) up to 190 blocks (152 inputs).
+constexpr int kF32Threads = 512;
+__global__ __launch_bounds__(kF32Threads) void xstage_fp32_kernel(XArgs a) {
+    // [kF32Kc][ls] complex samples, row r of input at r + r/16: across the lanes of a wave the
+    // 16 distinct (row block, half) operands of a read land in distinct bank pairs
+    extern __shared__ float2 zl[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int nhalf = a.n_blocks8 * (a.n_blocks8 + 1);   // two halves per lower-triangle block
+    const int groups = (nhalf + nthr - 1) / nthr;
     const int64_t ch = blockIdx.x / groups;
     const int g = blockIdx.x % groups;
-    const int rows = 8 * a.n_blocks8, ls = rows + 1;
+    const int rows = 8 * a.n_blocks8, ls = rows + rows / 16 + 1;
     const float2* __restrict__ z = (const float2*)((const char*)a.chan + ch * a.chan_stride);
 
-    // this thread's 8x8 block (A >= Bk) in the lower triangle of block rows
-    const int blk = g * 256 + tid;
-    const bool active = blk < a.n_blocks8 * (a.n_blocks8 + 1) / 2;
+    // this thread's 8x8 block (A >= Bk) in the lower triangle of block rows, and its half
+    const int hb = g * nthr + tid;
+    const bool active = hb < nhalf;
+    const int blk = hb >> 1, half = hb & 1;
     int A = 0, Bk = 0;
     if (active) {
         A = (int)((sqrtf(8.f * blk + 1.f) - 1.f) * 0.5f);
@@ -372,28 +392,43 @@ __global__ __launch_bounds__(256) void xstage_fp32_kernel(XArgs a) {
         while ((A + 1) * (A + 2) / 2 <= blk) ++A;
         Bk = blk - A * (A + 1) / 2;
     }
-    float vr[8][8], vi[8][8];
+    const int ra = 8 * A + 4 * half;               // first row of this half
+    float vr[4][8], vi[4][8];           // partial sums of the current fold
+    float tr[4][8], ti[4][8];           // running totals
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) { vr[i][j] = 0.f; vi[i][j] = 0.f; }
+        for (int j = 0; j < 8; ++j) { vr[i][j] = 0.f; vi[i][j] = 0.f; tr[i][j] = 0.f; ti[i][j] = 0.f; }
 
     for (int kc0 = 0; kc0 < a.n_c; kc0 += kF32Kc) {
+        if (kc0 % kF32Fold == 0 && kc0 > 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    tr[i][j] += vr[i][j];
+                    ti[i][j] += vi[i][j];
+                    vr[i][j] = 0.f;
+                    vi[i][j] = 0.f;
+                }
+        }
         __syncthreads();
-        for (int id = tid; id < rows * kF32Kc; id += 256) {
+        for (int id = tid; id < rows * kF32Kc; id += nthr) {
             const int row = id / kF32Kc, k = id % kF32Kc, col = kc0 + k;
             float2 v = make_float2(0.f, 0.f);
             if (row < a.M && col < a.n_c) v = z[((int64_t)(col / kKBlock) * a.M + row) * kKBlock + (col % kKBlock)];
-            zl[k * ls + row] = v;
+            zl[k * ls + row + (row >> 4)] = v;
         }
         __syncthreads();
         if (active) {
             for (int k = 0; k < kF32Kc; ++k) {
-                float2 xa[8], xb[8];
+                float2 xa[4], xb[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) { xa[i] = zl[k * ls + 8 * A + i]; xb[i] = zl[k * ls + 8 * Bk + i]; }
+                for (int i = 0; i < 4; ++i) xa[i] = zl[k * ls + ra + i + ((ra + i) >> 4)];
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 8; ++j) xb[j] = zl[k * ls + 8 * Bk + j + ((8 * Bk + j) >> 4)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
                         vr[i][j] = fmaf(xa[i].x, xb[j].x, fmaf(xa[i].y, xb[j].y, vr[i][j]));
@@ -405,14 +440,14 @@ __global__ __launch_bounds__(256) void xstage_fp32_kernel(XArgs a) {
     if (!active) return;
     const int64_t B = (int64_t)a.S * (a.S + 1) / 2;
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int aa = 8 * A + i, b = 8 * Bk + j;
+            const int aa = ra + i, b = 8 * Bk + j;
             if (aa < a.M && b < a.M && (aa >> 1) >= (b >> 1)) {
                 const int s1 = aa >> 1, s2 = b >> 1;
                 const int64_t idx = (ch * B + (int64_t)s1 * (s1 + 1) / 2 + s2) * 4 + 2 * (aa & 1) + (b & 1);
-                ((float2*)a.vis)[idx] = make_float2(vr[i][j], aa == b ? 0.f : vi[i][j]);
+                ((float2*)a.vis)[idx] = make_float2(tr[i][j] + vr[i][j], aa == b ? 0.f : ti[i][j] + vi[i][j]);
             }
         }
 }
@@ -428,10 +463,11 @@ hipError_t launch_xstage_mfma(int x_mode, const XArgs& a, hipStream_t st) {
 
 hipError_t launch_xstage_fp32(const XArgs& a, hipStream_t st) {
     if (a.n_chan <= 0) return hipSuccess;
-    const int nblk = a.n_blocks8 * (a.n_blocks8 + 1) / 2;
-    const int groups = (nblk + 255) / 256;
-    const size_t lds = (size_t)kF32Kc * (8 * a.n_blocks8 + 1) * sizeof(float2);
-    hipLaunchKernelGGL(xstage_fp32_kernel, dim3((unsigned)((int64_t)a.n_chan * groups)), dim3(256), lds, st, a);
+    const int nhalf = a.n_blocks8 * (a.n_blocks8 + 1);
+    const int nthr = nhalf < kF32Threads ? (nhalf + 63) / 64 * 64 : kF32Threads;
+    const int groups = (nhalf + nthr - 1) / nthr;
+    const size_t lds = (size_t)kF32Kc * (8 * a.n_blocks8 + (8 * a.n_blocks8) / 16 + 1) * sizeof(float2);
+    hipLaunchKernelGGL(xstage_fp32_kernel, dim3((unsigned)((int64_t)a.n_chan * groups)), dim3(nthr), lds, st, a);
     return hipGetLastError();
 }
 
