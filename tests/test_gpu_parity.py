@@ -5,9 +5,10 @@ Every case prints its name, sizes and seed before touching the GPU.  Inputs come
 
 Tolerances:
 * FP16-split mode: coherence error eps <= 1e-5 (the required 16-bit-mode bound).
-* FP32 mode: eps <= 1e-5.  Sequential FP32 accumulation of N_c products leaves a relative
-  error of about u*sqrt(N_c/3) (u = 2^-24), ~2e-6 rms at N_c = 3072, a few times that at
-  the maximum over all entries.
+* FP32 mode: eps <= 1e-6.  The X stage sums products over 128 channel samples into partial
+  sums that are folded into running totals, which leaves a relative error of about
+  u (128 / sqrt(N_c) + sqrt(N_c / 128)) / 6 (u = 2^-24): ~8e-8 rms at N_c = 3072, a few
+  times that at the maximum over all entries (a single running sum would leave ~9e-7 rms).
 * INT8 mode: the X stage is bit-exact on the same int8 stream; the requantised F output
   equals the oracle's except where the oracle's pre-rounding value lies within 1e-3 of a
   rounding boundary, where it may differ by exactly 1.
@@ -28,7 +29,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 EPS_FP16 = 1e-5
-EPS_FP32 = 1e-5
+EPS_FP32 = 1e-6
 
 
 def _say(msg):
