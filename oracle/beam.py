@@ -22,8 +22,15 @@ Readings where the paper is silent:
   ``Q = |X|^2 - |Y|^2``, ``U = 2 Re(X conj Y)``, ``V = 2 Im(X conj Y)``;
 * time integration: plain sums over ``n_int`` consecutive channel samples (N_c a multiple
   of n_int);
-* output resolution stays at 256 channels (the optional transform to 1 or 16 channels per
-  subband is not part of this reference).
+* output resolution (the paper transforms the 256 beamformed channels "to the requested
+  output resolution, often 1 or 16 channels per subband", and time resolution is traded for
+  frequency resolution within a subband): ``resolution_transform`` takes each channel
+  sample's C values back to C time samples with an inverse DFT (scaled 1/C, channel c
+  carrying frequency index c - C/2), joins the rows into one time series at the subband
+  sample rate, cuts it into consecutive groups of C_out samples and gives each group an
+  unnormalised forward C_out-point DFT (output channel c' carrying index c' - C_out/2).
+  C_out = 1 is the time series itself; C_out = C reproduces the input.  Stokes of the
+  transformed voltages are summed over n_int consecutive output samples.
 """
 
 from __future__ import annotations
@@ -33,7 +40,7 @@ import numpy as np
 from . import fx
 
 __all__ = ["beam_cycles", "beam_weights", "coherent_beams", "stokes", "integrate", "incoherent_stokes",
-           "beamform_block"]
+           "beamform_block", "resolution_transform", "transformed_stokes"]
 
 
 def beam_cycles(f_c: np.ndarray, dtau: np.ndarray) -> np.ndarray:
@@ -111,3 +118,32 @@ def beamform_block(x, history, h, bandpass, subband_freqs, sample_rate, delays, 
     if return_channelised:
         out["Z"] = Z
     return out
+
+
+def resolution_transform(B, C_out: int) -> np.ndarray:
+    """Beamformed voltages at C channels -> C_out channels (the reading in the module
+    docstring).  ``B`` complex [..., C, n_c] (channel axis -2, channel sample axis -1).
+    Returns complex [..., n_c * C / C_out, C_out]: output sample g, output channel c'.
+
+        u[j C + n] = (1/C) sum_c B[c, j] exp(+2 pi i n (c - C/2) / C),      n < C
+        O[g, c']   = sum_m u[g C_out + m] exp(-2 pi i m (c' - C_out/2) / C_out),  m < C_out
+    """
+    B = np.asarray(B, np.complex128)
+    *lead, C, n_c = B.shape
+    assert C % C_out == 0, (C, C_out)
+    n = np.arange(C)
+    E = np.exp(2j * np.pi * np.outer(n, np.arange(C) - C // 2) / C) / C      # [n, c]
+    u = np.einsum("nc,...cj->...jn", E, B).reshape(*lead, n_c * C)           # time t = j C + n
+    m = np.arange(C_out)
+    F = np.exp(-2j * np.pi * np.outer(m, np.arange(C_out) - C_out // 2) / C_out)   # [m, c']
+    return u.reshape(*lead, n_c * C // C_out, C_out) @ F
+
+
+def transformed_stokes(beams, C_out: int, which: str = "IQUV", n_int: int = 1) -> np.ndarray:
+    """Stokes of the transformed voltages of both polarisations, summed over n_int output
+    samples.  ``beams`` [..., P = 2, C, n_c] -> [..., n_c C / C_out / n_int, C_out, len(which)]."""
+    O = resolution_transform(beams, C_out)                 # [..., 2, G, C_out]
+    st = stokes(O[..., 0, :, :], O[..., 1, :, :], which)   # [..., G, len(which), C_out]
+    st = np.moveaxis(st, -3, -1)                           # [..., len(which), C_out, G]
+    st = integrate(st, n_int)                              # [..., len(which), C_out, G / n_int]
+    return np.moveaxis(st, -1, -3).swapaxes(-1, -2)        # [..., G / n_int, C_out, len(which)]

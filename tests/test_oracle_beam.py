@@ -146,3 +146,99 @@ def test_integration_sums_consecutive_samples():
     v = np.arange(24.0).reshape(2, 12)
     np.testing.assert_array_equal(ob.integrate(v, 4), [[6, 22, 38], [54, 70, 86]])
     np.testing.assert_array_equal(ob.integrate(v, 12), v.sum(axis=-1, keepdims=True))
+
+
+# ---- output resolution transform (256 channels -> C_out channels) ----------------------------
+
+@pytest.mark.parametrize("C_out", [256])
+def test_transform_to_the_same_resolution_is_the_identity(C_out):
+    rng = np.random.default_rng(70)
+    B = _rand_complex(rng, (3, C, 5), 2.0)
+    O = ob.resolution_transform(B, C_out)
+    assert O.shape == (3, 5, C)
+    assert np.max(np.abs(O - np.swapaxes(B, -1, -2))) <= 1e-12 * np.max(np.abs(B))
+
+
+def test_transform_to_one_channel_is_the_inverse_fft():
+    """C_out = 1: each channel sample's 256 values become 256 time samples, the library's
+    inverse FFT of the channels in natural frequency order (numpy.fft.ifftshift puts the
+    DC channel C/2 first), rows joined in time order."""
+    rng = np.random.default_rng(71)
+    B = _rand_complex(rng, (2, C, 4), 1.0)
+    O = ob.resolution_transform(B, 1)[..., 0]
+    ref = np.fft.ifft(np.fft.ifftshift(B, axes=-2), axis=-2)       # [2, C, 4]: time n, row j
+    ref = np.swapaxes(ref, -1, -2).reshape(2, -1)                  # t = j C + n
+    assert np.max(np.abs(O - ref)) <= 1e-14
+
+
+@pytest.mark.parametrize("C_out,m", [(16, 3), (16, -5), (4, 1), (2, 0)])
+def test_bin_centred_channel_lands_in_its_output_channel(C_out, m):
+    """A single 256-channel bin c0 = C/2 + (C/C_out) m with value A e^{i phi_j} carries the
+    frequency m / C_out cycles per sample: in the C_out-channel transform it lands in output
+    channel C_out/2 + m with |O| = C_out A / C and phase phi_j + 2 pi m (n0 / C_out) for the
+    group starting at time n0 of row j; every other output channel is zero."""
+    n_c, A = 3, 5.0
+    c0 = C // 2 + (C // C_out) * m
+    phi = np.array([0.3, -1.1, 2.0])
+    B = np.zeros((C, n_c), complex)
+    B[c0] = A * np.exp(1j * phi)
+    O = ob.resolution_transform(B, C_out)                          # [n_c C / C_out, C_out]
+    per_row = C // C_out
+    for g in range(O.shape[0]):
+        j, n0 = divmod(g, per_row)
+        n0 *= C_out
+        expect = C_out * A / C * np.exp(1j * (phi[j] + 2 * np.pi * m * n0 / C_out))
+        assert abs(O[g, C_out // 2 + m] - expect) <= 1e-12
+        others = np.delete(O[g], C_out // 2 + m)
+        assert np.max(np.abs(others)) <= 1e-12
+
+
+def test_transform_conserves_power():
+    """Parseval: sum over a row's time samples of |u|^2 = (1/C) sum_c |B_c|^2, and an
+    unnormalised C_out-point DFT multiplies the power of each group by C_out."""
+    rng = np.random.default_rng(72)
+    B = _rand_complex(rng, (C, 6), 3.0)
+    for C_out in (1, 16):
+        O = ob.resolution_transform(B, C_out)
+        got = np.sum(np.abs(O) ** 2)
+        assert got == pytest.approx(C_out * np.sum(np.abs(B) ** 2) / C, rel=1e-12)
+
+
+def test_transform_brute_force_loops():
+    """The defining double sum by Python loops with cmath on a tiny setting (8 channels)."""
+    rng = np.random.default_rng(73)
+    Cs, n_c = 8, 3
+    B = _rand_complex(rng, (Cs, n_c), 1.0)
+    for C_out in (1, 2, 4, 8):
+        u = []
+        for j in range(n_c):
+            for n in range(Cs):
+                u.append(sum(B[c, j] * cmath.exp(2j * math.pi * n * (c - Cs // 2) / Cs) for c in range(Cs)) / Cs)
+        exp = np.zeros((n_c * Cs // C_out, C_out), complex)
+        for g in range(exp.shape[0]):
+            for k in range(C_out):
+                exp[g, k] = sum(u[g * C_out + mm] * cmath.exp(-2j * math.pi * mm * (k - C_out // 2) / C_out)
+                                for mm in range(C_out))
+        assert np.max(np.abs(ob.resolution_transform(B, C_out) - exp)) <= 1e-12
+
+
+def test_transformed_stokes_brute_force():
+    """Stokes of the transformed X and Y voltages, summed over n_int output samples, by loops."""
+    rng = np.random.default_rng(74)
+    Cs, n_c, C_out, n_int = 8, 4, 2, 2
+    beams = _rand_complex(rng, (2, Cs, n_c), 1.0)
+    got = ob.transformed_stokes(beams, C_out, "IQUV", n_int)
+    X = ob.resolution_transform(beams[0], C_out)
+    Y = ob.resolution_transform(beams[1], C_out)
+    G = X.shape[0]
+    assert got.shape == (G // n_int, C_out, 4)
+    for go in range(G // n_int):
+        for k in range(C_out):
+            acc = [0.0] * 4
+            for g in range(go * n_int, go * n_int + n_int):
+                x, y = X[g, k], Y[g, k]
+                acc[0] += abs(x) ** 2 + abs(y) ** 2
+                acc[1] += abs(x) ** 2 - abs(y) ** 2
+                acc[2] += 2 * (x * y.conjugate()).real
+                acc[3] += 2 * (x * y.conjugate()).imag
+            assert np.allclose(got[go, k], acc, rtol=1e-12, atol=1e-12)

@@ -119,7 +119,8 @@ def test_planted_flag_mistake_is_caught(monkeypatch, name, mutant, pin, args):
         pin(*args)
 
 
-_orig_bm = {name: getattr(obm, name) for name in ("beam_weights", "stokes", "incoherent_stokes")}
+_orig_bm = {name: getattr(obm, name) for name in ("beam_weights", "stokes", "incoherent_stokes",
+                                                  "resolution_transform")}
 
 
 def _weights_conjugated(f_c, dtau):
@@ -138,11 +139,26 @@ def _incoherent_one_pol(Z, S, P=2, which="IQUV"):
     return _orig_bm["stokes"](Zp[:, :, 0], 0 * Zp[:, :, 1], which).sum(axis=1)
 
 
+def _transform_forward_sign(B, C_out):
+    return np.conj(_orig_bm["resolution_transform"](np.conj(B), C_out))
+
+
+def _transform_unshifted(B, C_out):
+    return _orig_bm["resolution_transform"](np.roll(np.asarray(B), -np.asarray(B).shape[-2] // 2, axis=-2), C_out)
+
+
+def _transform_unscaled(B, C_out):
+    return np.asarray(B).shape[-2] * _orig_bm["resolution_transform"](B, C_out)
+
+
 BEAM_MUTANTS = [
     ("beam_weights", _weights_conjugated, bpins.test_point_source_gains, ()),
     ("stokes", _stokes_u_v_swapped, bpins.test_point_source_gains, ()),
     ("incoherent_stokes", _incoherent_one_pol,
      bpins.test_coherent_power_is_the_quadratic_form_of_the_correlation_matrix, ()),
+    ("resolution_transform", _transform_forward_sign, bpins.test_transform_to_one_channel_is_the_inverse_fft, ()),
+    ("resolution_transform", _transform_unshifted, bpins.test_bin_centred_channel_lands_in_its_output_channel, (16, 3)),
+    ("resolution_transform", _transform_unscaled, bpins.test_transform_conserves_power, ()),
 ]
 
 
