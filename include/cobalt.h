@@ -239,6 +239,34 @@ int cobalt_beamform(cobalt_plan* plan, const void* d_in, const double* h_delays,
 int cobalt_beamform_channelized(cobalt_plan* plan, const void* d_chan, const cobalt_beam_params* beams,
                                 void* d_coherent, void* d_voltages, void* d_incoherent, void* stream);
 
+/* ---- output resolution of the beams --------------------------------------------------
+ * The paper forms beams at 256 channels per subband and then transforms them to the
+ * requested output resolution, often 1 or 16 channels per subband (sec. 7.5), trading time
+ * resolution for frequency resolution within the subband (sec. 5).  Per subband, beam and
+ * polarisation, the 256 channel values of each channel sample j go back to 256 time samples
+ *     u[256 j + n] = (1/256) sum_c B[c][j] exp(+2 pi i n (c - 128) / 256),
+ * and every group of c_out consecutive samples gets a forward DFT
+ *     O[g][c'] = sum_m u[g c_out + m] exp(-2 pi i m (c' - c_out/2) / c_out)
+ * (output channel c' ascending in frequency; c_out = 1 is the time series at the subband
+ * sample rate).  Layouts (float, beams fastest), G = N_c * 256 / c_out output samples:
+ *   d_voltages      [SB][256][N_c][P][NB] complex: the beamformer's voltage output
+ *   d_out_voltages  [SB][G][c_out][P][NB] complex
+ *   d_out_stokes    [SB][G / n_int][c_out][n_stokes][NB]: Stokes (as for the beamformer) of
+ *                   the transformed voltages summed over n_int consecutive output samples */
+typedef struct cobalt_transform_params {
+    int32_t n_beams;     /* NB >= 1 (as given to the beamformer)                              */
+    int32_t c_out;       /* output channels per subband: 1, 2, 4, 8 or 16                     */
+    int32_t n_stokes;    /* 1 (I) or 4 (I, Q, U, V); read only when Stokes are requested      */
+    int32_t n_int;       /* a power of two up to 256 / c_out; read only when Stokes are requested */
+    int32_t reserved0;   /* must be 0                                                         */
+} cobalt_transform_params;
+
+/* Transform beamformed voltages of a 256-channel plan to c_out channels; either output may
+ * be NULL (not computed), not both.  Stateless (ordered by the stream alone).  Errors: EINVAL,
+ * EUNSUPPORTED (plan not at 256 channels, c_out), EDEVICE. */
+int cobalt_beam_transform(cobalt_plan* plan, const void* d_voltages, const cobalt_transform_params* params,
+                          void* d_out_voltages, void* d_out_stokes, void* stream);
+
 /* X stage only, on a caller-provided channelised buffer in this plan's mode and layout
  * (positions >= N_c are ignored).  Stateless (see above).  Errors: EINVAL, EDEVICE. */
 int cobalt_correlate_channelized(cobalt_plan* plan, const void* d_chan, void* d_vis,

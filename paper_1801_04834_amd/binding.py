@@ -24,7 +24,8 @@ _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW"
 
 EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_fp16_prescale_max", "cobalt_plan_query", "cobalt_correlate",
             "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
-            "cobalt_beamform_channelized", "cobalt_correlate_channelized", "cobalt_reset_history",
+            "cobalt_beamform_channelized", "cobalt_beam_transform", "cobalt_correlate_channelized",
+            "cobalt_reset_history",
             "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_device_fanout", "cobalt_mfma_probe", "cobalt_plan_destroy",
             "cobalt_last_error", "cobalt_service_create", "cobalt_service_open", "cobalt_service_query",
             "cobalt_service_submit",
@@ -68,6 +69,12 @@ class BeamParams(ct.Structure):
                 ("reserved0", ct.c_int32), ("d_beam_dtau", ct.c_void_p)]
 
 
+class TransformParams(ct.Structure):
+    """``cobalt_transform_params``."""
+    _fields_ = [("n_beams", ct.c_int32), ("c_out", ct.c_int32), ("n_stokes", ct.c_int32), ("n_int", ct.c_int32),
+                ("reserved0", ct.c_int32)]
+
+
 class ServiceStats(ct.Structure):
     _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("dropped", ct.c_int64),
                 ("late", ct.c_int64), ("p50_latency_s", ct.c_double), ("p99_latency_s", ct.c_double),
@@ -101,6 +108,7 @@ def load_library():
     lib.cobalt_beamform.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BeamParams), vp, vp, vp, vp]
     lib.cobalt_beamform_channelized.argtypes = [vp, vp, ct.POINTER(BeamParams), vp, vp, vp, vp]
     lib.cobalt_correlate_channelized.argtypes = [vp, vp, vp, vp]
+    lib.cobalt_beam_transform.argtypes = [vp, vp, ct.POINTER(TransformParams), vp, vp, vp]
     lib.cobalt_reset_history.argtypes = [vp, vp]
     lib.cobalt_apply_gains.argtypes = [vp, vp, vp, vp, vp]
     lib.cobalt_apply_gains_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -413,6 +421,27 @@ class Plan:
         return self._beam_call(self._lib.cobalt_beamform_channelized,
                                self._dev(chan, self.chan_shape, self.chan_dtype, "chan"), None, dtau, n_stokes, n_int,
                                coherent, voltages, incoherent, stream)
+
+    def transform_shapes(self, n_beams, c_out, n_stokes=4, n_int=1):
+        """Shapes of the transformed voltages and of their Stokes (``cobalt_beam_transform``)."""
+        G = self.n_c * self.C // c_out
+        return (self.SB, G, c_out, 2, n_beams, 2), (self.SB, G // n_int, c_out, n_stokes, n_beams)
+
+    def beam_transform(self, voltages, c_out, n_stokes=4, n_int=1, out_voltages=None, out_stokes=None, stream=None):
+        """256 -> c_out channels of the beamformer's voltages (float32 [SB][256][N_c][2][NB][2]);
+        outputs are caller tensors of ``transform_shapes`` (either may be None, not both)."""
+        t = self._torch
+        if voltages.dim() != 6:
+            raise ValueError("voltages: need float32 [SB][C][N_c][2][NB][2]")
+        nb = voltages.shape[4]
+        vs = (self.SB, self.C, self.n_c, 2, nb, 2)
+        ov, osk = self.transform_shapes(nb, c_out, n_stokes, n_int)
+        tp = TransformParams(nb, c_out, n_stokes, n_int, 0)
+        ptr = lambda x, shp, name: None if x is None else self._dev(x, shp, t.float32, name)  # noqa: E731
+        _check(self._lib.cobalt_beam_transform(self._ptr, self._dev(voltages, vs, t.float32, "voltages"), ct.byref(tp),
+                                               ptr(out_voltages, ov, "out_voltages"), ptr(out_stokes, osk, "out_stokes"),
+                                               _stream_handle(t, stream, self.device)))
+        return out_voltages, out_stokes
 
     def correlate_channelized(self, chan, out=None, stream=None):
         """X stage only on a channelised tensor; returns the visibility tensor."""

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcobalt.so")
-SOURCES = ["plan.hip", "fstage.hip", "xstage.hip", "gains.hip", "flags.hip", "beam.hip", "service.hip", "probe.hip"]
+SOURCES = ["plan.hip", "fstage.hip", "xstage.hip", "gains.hip", "flags.hip", "beam.hip", "beamxf.hip", "service.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -75,6 +75,14 @@ struct BeamArgs {
     float vscale;            // 2^-k: undoes the FP16-split prescale
 };
 
+// Output-resolution transform of beamformed voltages (256 channels -> c_out channels).
+struct TfArgs {
+    const void* vin;         // [SB][256][N_c][P][NB] float (re, im): the beamformer's voltages
+    void* vout;              // [SB][N_c 256 / c_out][c_out][P][NB] float (re, im), or null
+    void* sout;              // [SB][N_c 256 / c_out / n_int][c_out][n_stokes][NB] float, or null
+    int32_t SB, n_c, NB, n_bg, c_out, n_stokes, n_int;
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_fstage(int sample_type, int x_mode, const FArgs& a, int n_streams, hipStream_t st);
 hipError_t launch_xstage_mfma(int x_mode, const XArgs& a, hipStream_t st);
@@ -82,6 +90,7 @@ hipError_t launch_xstage_fp32(const XArgs& a, hipStream_t st);
 hipError_t launch_chanflags(const FlagArgs& a, hipStream_t st);
 hipError_t launch_weights(const uint32_t* cflag, int32_t* weights, int S, int SB, int n_c, int n_words, hipStream_t st);
 hipError_t launch_beamformer(const BeamArgs& a, hipStream_t st);
+hipError_t launch_beam_transform(const TfArgs& a, hipStream_t st);
 hipError_t launch_zero_fill(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_mfma_probe(int x_mode, int64_t iters, int workgroups, float* sink, hipStream_t st);

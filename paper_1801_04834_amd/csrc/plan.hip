@@ -298,18 +298,17 @@ int run_flags(cobalt_plan* p, const uint32_t* d_flags, int64_t row_len, const in
     return COBALT_OK;
 }
 
-int run_fstage(cobalt_plan* p, const void* d_in, int64_t row_len, const double* d_delays, const int32_t* d_coarse,
-               const uint32_t* cflag, void* d_chan, hipStream_t st) {
-    const Sizes& z = p->z;
-    if (z.n_c == 0) return COBALT_OK;       // empty block: nothing to filter, history unchanged
+FArgs make_fargs(const Sizes& z, const cobalt_config& cfg, const void* d_in, int64_t row_len, const void* hist_old,
+                 void* hist_new, const float* fir, const float* bscale, const double* fsb, const double* d_delays,
+                 const int32_t* d_coarse, const uint32_t* cflag, void* d_chan) {
     FArgs a{};
     a.in = d_in;
-    a.hist_old = p->d_hist[p->hist_cur];
-    a.hist_new = p->d_hist[p->hist_cur ^ 1];
+    a.hist_old = hist_old;
+    a.hist_new = hist_new;
     a.out = d_chan;
-    a.fir = p->d_fir;
-    a.bscale = p->d_bscale;
-    a.f_sb = p->d_fsb;
+    a.fir = fir;
+    a.bscale = bscale;
+    a.f_sb = fsb;
     a.delays = d_delays;
     a.coarse = d_coarse;
     a.cflag = cflag;
@@ -323,16 +322,12 @@ int run_fstage(cobalt_plan* p, const void* d_in, int64_t row_len, const double* 
     a.pitch = (int)z.pitch;
     a.n_chunks = (int)((z.pitch + kFChunk - 1) / kFChunk);
     a.n_kb = (int)(z.pitch / kKBlock);
-    a.df = p->cfg.sample_rate_hz / (double)z.C;
+    a.df = cfg.sample_rate_hz / (double)z.C;
     a.C = (int)z.C;
-    hipError_t e = launch_fstage(p->cfg.sample_type, p->cfg.x_mode, a, (int)z.streams, st);
-    if (e != hipSuccess) return hip_fail(e, "F-stage launch");
-    p->hist_cur ^= 1;
-    return COBALT_OK;
+    return a;
 }
 
-int run_xstage(cobalt_plan* p, const void* d_chan, void* d_vis, hipStream_t st) {
-    const Sizes& z = p->z;
+XArgs make_xargs(const Sizes& z, const cobalt_config& cfg, const void* d_chan, void* d_vis) {
     XArgs a{};
     a.chan = d_chan;
     a.vis = d_vis;
@@ -344,10 +339,30 @@ int run_xstage(cobalt_plan* p, const void* d_chan, void* d_vis, hipStream_t st) 
     a.n_chan = (int)(z.SB * z.C);
     a.n_blocks8 = (int)((z.M + 7) / 8);
     a.n_kb = (int)(z.pitch / kKBlock);
-    a.out_scale = std::ldexp(1.0f, -2 * p->cfg.fp16_prescale_log2);
-    hipError_t e = p->cfg.x_mode == COBALT_X_FP32 ? launch_xstage_fp32(a, st) : launch_xstage_mfma(p->cfg.x_mode, a, st);
+    a.out_scale = std::ldexp(1.0f, -2 * cfg.fp16_prescale_log2);
+    return a;
+}
+
+int launch_x(const cobalt_config& cfg, const XArgs& a, hipStream_t st) {
+    hipError_t e = cfg.x_mode == COBALT_X_FP32 ? launch_xstage_fp32(a, st) : launch_xstage_mfma(cfg.x_mode, a, st);
     if (e != hipSuccess) return hip_fail(e, "X-stage launch");
     return COBALT_OK;
+}
+
+int run_fstage(cobalt_plan* p, const void* d_in, int64_t row_len, const double* d_delays, const int32_t* d_coarse,
+               const uint32_t* cflag, void* d_chan, hipStream_t st) {
+    const Sizes& z = p->z;
+    if (z.n_c == 0) return COBALT_OK;       // empty block: nothing to filter, history unchanged
+    const FArgs a = make_fargs(z, p->cfg, d_in, row_len, p->d_hist[p->hist_cur], p->d_hist[p->hist_cur ^ 1], p->d_fir,
+                               p->d_bscale, p->d_fsb, d_delays, d_coarse, cflag, d_chan);
+    hipError_t e = launch_fstage(p->cfg.sample_type, p->cfg.x_mode, a, (int)z.streams, st);
+    if (e != hipSuccess) return hip_fail(e, "F-stage launch");
+    p->hist_cur ^= 1;
+    return COBALT_OK;
+}
+
+int run_xstage(cobalt_plan* p, const void* d_chan, void* d_vis, hipStream_t st) {
+    return launch_x(p->cfg, make_xargs(p->z, p->cfg, d_chan, d_vis), st);
 }
 
 struct CallLock {
@@ -649,6 +664,47 @@ int cobalt_beamform_channelized(cobalt_plan* p, const void* d_chan, const cobalt
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
     return run_beam(p, d_chan, bp, d_coherent, d_voltages, d_incoherent, (hipStream_t)stream);
+}
+
+int cobalt_beam_transform(cobalt_plan* p, const void* d_voltages, const cobalt_transform_params* tp,
+                          void* d_out_voltages, void* d_out_stokes, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(COBALT_EINVAL, "plan is NULL");
+    if (!tp) return fail(COBALT_EINVAL, "transform parameters are NULL");
+    const Sizes& z = p->z;
+    if (z.C != 256) return fail(COBALT_EUNSUPPORTED, "the transform takes 256-channel voltages (plan has %lld)", (long long)z.C);
+    if (tp->n_beams < 1) return fail(COBALT_EINVAL, "n_beams must be >= 1 (got %d)", tp->n_beams);
+    const int co = tp->c_out;
+    if (co != 1 && co != 2 && co != 4 && co != 8 && co != 16)
+        return fail(COBALT_EUNSUPPORTED, "c_out must be 1, 2, 4, 8 or 16 (got %d)", co);
+    if (tp->reserved0 != 0) return fail(COBALT_EINVAL, "reserved0 must be 0");
+    if (!d_out_voltages && !d_out_stokes) return fail(COBALT_EINVAL, "no output requested");
+    if (d_out_stokes) {
+        if (tp->n_stokes != 1 && tp->n_stokes != 4) return fail(COBALT_EINVAL, "n_stokes must be 1 or 4 (got %d)", tp->n_stokes);
+        const int per_row = 256 / co, ni = tp->n_int;
+        if (ni < 1 || (ni & (ni - 1)) != 0 || ni > per_row)
+            return fail(COBALT_EINVAL, "n_int must be a power of two up to %d (got %d)", per_row, ni);
+    }
+    if ((!d_voltages && z.n_c > 0) || ((uintptr_t)d_voltages | (uintptr_t)d_out_voltages | (uintptr_t)d_out_stokes) % 16)
+        return fail(COBALT_EINVAL, "device pointers must be non-NULL and 16-byte aligned");
+    if ((int64_t)z.SB * z.n_c * ((tp->n_beams + 15) / 16) >= ((int64_t)1 << 31))
+        return fail(COBALT_EUNSUPPORTED, "too many subbands x channel samples x beam groups for one launch");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
+    TfArgs a{};
+    a.vin = d_voltages;
+    a.vout = d_out_voltages;
+    a.sout = d_out_stokes;
+    a.SB = (int)z.SB;
+    a.n_c = (int)z.n_c;
+    a.NB = tp->n_beams;
+    a.n_bg = (tp->n_beams + 15) / 16;
+    a.c_out = co;
+    a.n_stokes = d_out_stokes ? tp->n_stokes : 0;
+    a.n_int = d_out_stokes ? tp->n_int : 1;
+    hipError_t e = launch_beam_transform(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "transform launch");
+    return COBALT_OK;
 }
 
 // Stateless with respect to the plan (reads only its immutable sizes): ordered by the

@@ -147,3 +147,82 @@ def test_beamformer_rejects_bad_parameters():
         with pytest.raises(binding.CobaltError) as ei:
             plan.beamform_channelized(plan.empty_chan(), dt, 4, 8, coherent=coh)
         assert ei.value.code == binding.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("c_out,n_stokes,n_int", [(16, 4, 1), (16, 1, 16), (1, 4, 64), (4, 4, 8), (2, 1, 1), (8, 4, 32)])
+def test_output_resolution_transform_matches_oracle(c_out, n_stokes, n_int):
+    """The beamformer's 256-channel voltages transformed to c_out channels on the GPU: against
+    the oracle's transform of the same GPU voltages (FP32 transform error only: <= 2e-6 of the
+    rms), and against the oracle's whole chain (beams in FP64, then the transform: the voltage
+    tolerance 2e-5 rms; Stokes |dS| <= 4e-5 I + 1e-6 mean(I)).  37 beams: three groups of 16,
+    the last partial."""
+    from paper_1801_04834_amd import binding
+    S, NB, n_c, SB = 6, 37, 24, 2
+    seed = 2900 + c_out + n_int
+    w = _work(S, SB, n_c, seed)
+    rng = np.random.default_rng(seed)
+    dtau = rng.uniform(-4e-6, 4e-6, (NB, S))
+    _say(f"CASE beam transform c_out={c_out} n_stokes={n_stokes} n_int={n_int} S={S} NB={NB} n_c={n_c}")
+    x = w.block(0)
+    o = _oracle(w, [x], dtau, 4, 1)[0]
+    which = "IQUV" if n_stokes == 4 else "I"
+    with binding.plan_for(w) as plan:
+        _, vs, _ = plan.beam_shapes(NB, 4, 1)
+        volt = torch.empty(vs, dtype=torch.float32, device="cuda")
+        plan.beamform(torch.from_numpy(x).cuda(), w.delays(0), torch.from_numpy(dtau).cuda(), 4, 1, voltages=volt)
+        ov, osk = plan.transform_shapes(NB, c_out, n_stokes, n_int)
+        tv = torch.full(ov, np.nan, dtype=torch.float32, device="cuda")
+        ts = torch.full(osk, np.nan, dtype=torch.float32, device="cuda")
+        plan.beam_transform(volt, c_out, n_stokes, n_int, out_voltages=tv, out_stokes=ts)
+        # Stokes only (no voltage output): the same values
+        ts2 = torch.full(osk, np.nan, dtype=torch.float32, device="cuda")
+        plan.beam_transform(volt, c_out, n_stokes, n_int, out_stokes=ts2)
+        torch.cuda.synchronize()
+        assert torch.equal(ts, ts2)
+        vg = volt.cpu().numpy().astype(np.float64)               # [SB, C, n_c, P, NB, 2]
+        Tg = tv.cpu().numpy().astype(np.float64)                 # [SB, G, c_out, P, NB, 2]
+        Sg = ts.cpu().numpy().astype(np.float64)                 # [SB, G/n_int, c_out, n_stokes, NB]
+    Tg = Tg[..., 0] + 1j * Tg[..., 1]
+    # oracle transform of the GPU's own voltages: [SB, NB, P, C, n_c] -> [SB, NB, P, G, c_out]
+    Bg = np.transpose(vg[..., 0] + 1j * vg[..., 1], (0, 4, 3, 1, 2))
+    ref_own = ob.resolution_transform(Bg, c_out)
+    got = np.transpose(Tg, (0, 4, 3, 1, 2))                     # [SB, NB, P, G, c_out]
+    rms = np.sqrt(np.mean(np.abs(ref_own) ** 2))
+    e_own = float(np.max(np.abs(got - ref_own))) / rms
+    # the whole chain: oracle beams [SB, C, NB, P, n_c] -> [SB, NB, P, C, n_c]
+    Bo = np.transpose(o["beams"], (0, 2, 3, 1, 4))
+    ref = ob.resolution_transform(Bo, c_out)
+    e_chain = float(np.max(np.abs(got - ref))) / np.sqrt(np.mean(np.abs(ref) ** 2))
+    st = ob.transformed_stokes(Bo, c_out, which, n_int)         # [SB, NB, G/n_int, c_out, n_stokes]
+    Sgt = np.transpose(Sg, (0, 4, 1, 2, 3))
+    I = st[..., 0:1]
+    err = np.abs(Sgt - st)
+    worst = float(np.max(err / (np.abs(I) + np.mean(np.abs(I)))))
+    _say(f"  voltages vs oracle transform of the same input {e_own:.2e} rms, vs oracle chain {e_chain:.2e} rms; "
+         f"Stokes worst {worst:.2e}")
+    assert e_own <= 2e-6
+    assert e_chain <= 2e-5
+    assert np.all(err <= 4e-5 * np.abs(I) + 1e-6 * np.mean(np.abs(I)))
+
+
+def test_output_resolution_transform_rejects_bad_settings():
+    from paper_1801_04834_amd import binding
+    w = _work(2, 1, 16, 5)
+    with binding.plan_for(w) as plan:
+        _, vs, _ = plan.beam_shapes(3, 4, 1)
+        volt = torch.zeros(vs, dtype=torch.float32, device="cuda")
+        sink = torch.empty(1 << 20, device="cuda")          # never written: every call is refused
+        for c_out, n_int, code in ((3, 1, binding.EUNSUPPORTED), (32, 1, binding.EUNSUPPORTED),
+                                   (16, 32, binding.EINVAL), (16, 3, binding.EINVAL)):
+            tp = binding.TransformParams(3, c_out, 4, n_int, 0)
+            rc = plan._lib.cobalt_beam_transform(plan._ptr, binding.ct.c_void_p(volt.data_ptr()), binding.ct.byref(tp),
+                                                 None, binding.ct.c_void_p(sink.data_ptr()), None)
+            assert rc == code, (c_out, n_int, rc)
+    w64 = synth.Workload(name="beam64", S=2, SB=1, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, N=64 * 16,
+                         fp16_prescale_log2=-1)
+    with binding.plan_for(w64) as plan:
+        tp = binding.TransformParams(3, 16, 4, 1, 0)
+        buf = torch.empty(1 << 20, device="cuda")
+        rc = plan._lib.cobalt_beam_transform(plan._ptr, binding.ct.c_void_p(buf.data_ptr()), binding.ct.byref(tp),
+                                             binding.ct.c_void_p(buf.data_ptr()), None, None)
+        assert rc == binding.EUNSUPPORTED
