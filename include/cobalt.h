@@ -405,6 +405,23 @@ int cobalt_service_destroy(cobalt_service* svc);
 /* Message for the last service error on this host thread. */
 const char* cobalt_service_last_error(void);
 
+/* cobalt_correlate without a plan, for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid allocation): one block of
+ * the full FX chain for setting cfg, allocating nothing.  Its intermediate data (the
+ * channelised block between the F and X stages, the tables, a zero or discarded history)
+ * live in a fixed scratch array of 256 MiB that every GPU the library runs on holds for the
+ * life of the process; settings whose channelised block and tables exceed it are refused
+ * (EUNSUPPORTED: use a plan).  The FIR history is the caller's: d_hist_in holds the
+ * (T-1)*C samples of each stream that precede the block ([S*P*SB][(T-1)*C] samples of the
+ * input type, stream (s*P + p)*SB + sb; NULL = zeros, a first block) and d_hist_out
+ * receives those that follow it (NULL = discarded); they must not be the same buffer.
+ * Every call on one GPU uses that GPU's one scratch array: calls that overlap on the device
+ * (on different streams, or from several host threads) race and must be ordered by the
+ * caller.  Host arrays (cfg tables, h_delays [S][2]) may be reused as soon as the call
+ * returns.  samples_per_block must be > 0.  Errors: EINVAL, EUNSUPPORTED, EOVERFLOW, EDEVICE. */
+int cobalt_correlate_noalloc(const cobalt_config* cfg, const void* d_in, const double* h_delays,
+                             const void* d_hist_in, void* d_hist_out, void* d_vis, void* stream);
+
 /* Wait for the plan's last call, then free everything it owns.  NULL is a no-op.
  * Errors: EDEVICE (the plan is freed anyway). */
 int cobalt_plan_destroy(cobalt_plan* plan);

@@ -23,7 +23,7 @@ _CODES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", EOVERFLOW: "EOVERFLOW"
           EBUSY: "EBUSY", EDEVICE: "EDEVICE"}
 
 EXPORTED = ["cobalt_plan_create", "cobalt_estimate_bytes", "cobalt_fp16_prescale_max", "cobalt_plan_query", "cobalt_correlate",
-            "cobalt_channelize", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
+            "cobalt_channelize", "cobalt_correlate_noalloc", "cobalt_correlate_ex", "cobalt_channelize_ex", "cobalt_beamform",
             "cobalt_beamform_channelized", "cobalt_beam_transform", "cobalt_correlate_channelized",
             "cobalt_reset_history",
             "cobalt_apply_gains", "cobalt_apply_gains_adjoint", "cobalt_device_copy", "cobalt_device_fanout", "cobalt_mfma_probe", "cobalt_plan_destroy",
@@ -103,6 +103,7 @@ def load_library():
     lib.cobalt_plan_query.argtypes = [vp, ct.POINTER(PlanInfo)]
     lib.cobalt_correlate.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
     lib.cobalt_channelize.argtypes = [vp, vp, ct.POINTER(ct.c_double), vp, vp]
+    lib.cobalt_correlate_noalloc.argtypes = [ct.POINTER(Config), vp, ct.POINTER(ct.c_double), vp, vp, vp, vp]
     lib.cobalt_correlate_ex.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BlockExt), vp, vp]
     lib.cobalt_channelize_ex.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BlockExt), vp, vp]
     lib.cobalt_beamform.argtypes = [vp, vp, ct.POINTER(ct.c_double), ct.POINTER(BeamParams), vp, vp, vp, vp]
@@ -498,6 +499,38 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def correlate_noalloc(x, delays, out, hist_in=None, hist_out=None, stream=None, **kw):
+    """One block of the FX chain without a plan (``cobalt_correlate_noalloc``): keywords as
+    ``Plan``; ``x`` input [S][2][SB][N][2], ``out`` visibilities [SB][C][B][4][2], ``hist_in``
+    / ``hist_out`` the carried FIR history [S*2*SB][(T-1)*C][2] in the input dtype (None: zeros
+    / discarded); all contiguous tensors on the current device.  Returns ``out``."""
+    import torch
+    cfg, keep = make_config(**kw)
+    S, SB, N = kw["n_stations"], kw["n_subbands"], kw["samples_per_block"]
+    C, T = kw.get("n_channels", 64), kw.get("n_taps", 16)
+    B = S * (S + 1) // 2
+    idt = {CI8: torch.int8, CI16: torch.int16, CF32: torch.float32}[kw["sample_type"]]
+    vdt = torch.int32 if kw["x_mode"] == X_INT8 else torch.float32
+
+    def chk(t, shape, dt, name):
+        if t is None:
+            return None
+        if not t.is_cuda or t.dtype != dt or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name}: need contiguous {dt} {tuple(shape)} on the GPU, got {t.dtype} {tuple(t.shape)}")
+        return ct.c_void_p(t.data_ptr())
+
+    d = np.ascontiguousarray(delays, np.float64).reshape(-1)
+    if d.size != 2 * S:
+        raise ValueError(f"delays: need {S}x2 float64 seconds")
+    hshape = (S * 2 * SB, (T - 1) * C, 2)
+    args = (ct.byref(cfg), chk(x, (S, 2, SB, N, 2), idt, "x"), d.ctypes.data_as(ct.POINTER(ct.c_double)),
+            chk(hist_in, hshape, idt, "hist_in"), chk(hist_out, hshape, idt, "hist_out"),
+            chk(out, (SB, C, B, 4, 2), vdt, "out"), _stream_handle(torch, stream, x.device))
+    _check(load_library().cobalt_correlate_noalloc(*args))
+    del keep
+    return out
 
 
 def plan_for(workload, **overrides):

@@ -795,6 +795,98 @@ int cobalt_mfma_probe(int32_t x_mode, int64_t iterations, int32_t workgroups, fl
     return COBALT_OK;
 }
 
+}  // extern "C"
+
+// ---- the entry point that allocates nothing --------------------------------------------
+// Scratch for cobalt_correlate_noalloc: the channelised block between its F and X stages,
+// the zero or discarded FIR history when the caller passes none, and the per-call tables.
+// Every GPU the library runs on holds one copy for the life of the process.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[64] = {};      // device address of `scratch` per device, looked up once
+
+// The device address of this device's `scratch` (the host-side symbol is only a stand-in).
+int scratch_base(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(COBALT_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (char*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return COBALT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cobalt_correlate_noalloc(const cobalt_config* cfg, const void* d_in, const double* h_delays, const void* d_hist_in,
+                             void* d_hist_out, void* d_vis, void* stream) {
+    g_last_error.clear();
+    Sizes z;
+    int rc = validate(cfg, &z);
+    if (rc != COBALT_OK) return rc;
+    if (z.N == 0) return fail(COBALT_EINVAL, "samples_per_block must be > 0 for this entry point");
+    if (!d_in || !h_delays || !d_vis) return fail(COBALT_EINVAL, "d_in, h_delays or d_vis is NULL");
+    if (((uintptr_t)d_in | (uintptr_t)d_vis | (uintptr_t)d_hist_in | (uintptr_t)d_hist_out) % 16)
+        return fail(COBALT_EINVAL, "device pointers must be 16-byte aligned");
+    if (d_hist_in && d_hist_in == d_hist_out)
+        return fail(COBALT_EINVAL, "d_hist_in and d_hist_out must differ (the F stage reads one while writing the other)");
+    for (int i = 0; i < 2 * z.S; ++i)
+        if (!std::isfinite(h_delays[i])) return fail(COBALT_EINVAL, "h_delays[%d] is not finite", i);
+    // scratch layout: channelised block | zero history | discarded history | FIR | bandpass x scale |
+    // subband frequencies | delays
+    const int64_t hist = round_up(z.hist_bytes, 256);
+    const int64_t o_chan = 0;
+    const int64_t o_hzero = o_chan + round_up(z.chan_bytes, 256);
+    const int64_t o_hdrop = o_hzero + (d_hist_in ? 0 : hist);
+    const int64_t o_fir = o_hdrop + (d_hist_out ? 0 : hist);
+    const int64_t o_bsc = o_fir + round_up(kT * z.C * 4, 256);
+    const int64_t o_fsb = o_bsc + round_up(z.C * 4, 256);
+    const int64_t o_del = o_fsb + round_up(z.SB * 8, 256);
+    const int64_t total = o_del + round_up(z.S * 16, 256);
+    if (total > (int64_t)kScratchBytes)
+        return fail(COBALT_EUNSUPPORTED,
+                    "this setting needs %lld bytes of scratch; the no-allocation entry point has %zu (use a plan)",
+                    (long long)total, kScratchBytes);
+    char* base = nullptr;
+    rc = scratch_base(&base);
+    if (rc != COBALT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    float bscale[256];
+    const double mode_scale = cfg->x_mode == COBALT_X_FP16_SPLIT ? std::ldexp(1.0, cfg->fp16_prescale_log2)
+                              : cfg->x_mode == COBALT_X_INT8   ? (double)cfg->requant_gain
+                                                               : 1.0;
+    for (int c = 0; c < z.C; ++c) bscale[c] = (float)((cfg->h_bandpass ? (double)cfg->h_bandpass[c] : 1.0) * mode_scale);
+    // host -> scratch copies from pageable memory return once the source has been read
+    hipError_t e = hipMemcpyAsync(base + o_fir, cfg->h_fir, sizeof(float) * kT * z.C, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + o_bsc, bscale, sizeof(float) * z.C, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + o_fsb, cfg->h_subband_freq_hz, sizeof(double) * z.SB, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + o_del, h_delays, sizeof(double) * 2 * z.S, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    if (!d_hist_in) {
+        e = launch_zero_fill(base + o_hzero, hist, st);      // a fill kernel, no memset node
+        if (e != hipSuccess) return hip_fail(e, "history fill");
+    }
+    const FArgs a = make_fargs(z, *cfg, d_in, z.N, d_hist_in ? d_hist_in : base + o_hzero,
+                               d_hist_out ? d_hist_out : base + o_hdrop, (const float*)(base + o_fir),
+                               (const float*)(base + o_bsc), (const double*)(base + o_fsb),
+                               (const double*)(base + o_del), nullptr, nullptr, base + o_chan);
+    e = launch_fstage(cfg->sample_type, cfg->x_mode, a, (int)z.streams, st);
+    if (e != hipSuccess) return hip_fail(e, "F-stage launch");
+    return launch_x(*cfg, make_xargs(z, *cfg, base + o_chan, d_vis), st);
+}
+
 int cobalt_plan_destroy(cobalt_plan* p) {
     g_last_error.clear();
     if (!p) return COBALT_OK;

@@ -135,3 +135,16 @@ def test_copies_reject_bad_arguments_before_touching_a_gpu(ptrs, nbytes):
     d0, d1, s = (ct.c_void_p(p) for p in ptrs)
     assert lib.cobalt_device_fanout(d0, d1, s, ct.c_size_t(nbytes), None) == binding.EINVAL
 
+
+def test_noalloc_refuses_settings_beyond_its_scratch_before_touching_a_gpu():
+    """The 16-bit share needs a 15 GB channelised block: cobalt_correlate_noalloc refuses it
+    (EUNSUPPORTED) from the sizes alone; the dummy device pointers are never dereferenced."""
+    import ctypes as ct
+    lib = _lib()
+    cfg, keep = binding.make_config(**_kw(fp16_prescale_log2=-1))
+    d = np.zeros(2 * 76)
+    p = ct.c_void_p(256)
+    rc = lib.cobalt_correlate_noalloc(ct.byref(cfg), p, d.ctypes.data_as(ct.POINTER(ct.c_double)), None, None, p, None)
+    assert rc == binding.EUNSUPPORTED
+    assert "scratch" in lib.cobalt_last_error().decode()
+    del keep
