@@ -229,9 +229,38 @@ def time_beamformer(torch, binding, synth, steps, device):
     torch.cuda.synchronize()
     f_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
     b_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    # output resolution: the same beams as complex voltages (rows padded to 128 beams, whole
+    # 128-byte lines per 16 beams), transformed to 16 channels per subband, Stokes I summed over
+    # 16 output samples; then the same transform writing the transformed voltages
+    del coh
+    NBS = (NB + 15) // 16 * 16
+    _, vs, _ = plan.beam_shapes(NB, 1, 1, voltage_stride=NBS)
+    volt = torch.empty(vs, dtype=torch.float32, device=device)
+    tvs, tsz = plan.transform_shapes(NB, 16, 1, 16, voltage_stride=NBS)
+    ts = torch.empty(tsz, dtype=torch.float32, device=device)
+    tv = torch.empty(tvs, dtype=torch.float32, device=device)
+    plan.beamform_channelized(chan, dtau, 1, 1, voltages=volt)
+    plan.beam_transform(volt, 16, 1, 16, out_stokes=ts, n_beams=NB)
+    plan.beam_transform(volt, 16, 1, 16, out_voltages=tv, n_beams=NB)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        plan.beamform_channelized(chan, dtau, 1, 1, voltages=volt)
+        ev[k][1].record()
+        plan.beam_transform(volt, 16, 1, 16, out_stokes=ts, n_beams=NB)
+        ev[k][2].record()
+        plan.beam_transform(volt, 16, 1, 16, out_voltages=tv, n_beams=NB)
+        ev[k][3].record()
+    torch.cuda.synchronize()
+    beam_voltage_bytes = volt.numel() * 4 * NB // NBS        # the beams, not the padding
+    xf = {"voltages_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+          "transform_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
+          "transform_voltages_ms": float(np.mean([e[2].elapsed_time(e[3]) for e in ev])),
+          "voltage_bytes": beam_voltage_bytes, "stokes_bytes": ts.numel() * 4, "stride": NBS}
     plan.close()
-    del x, chan, coh, inc
-    return w, NB, n_int, f_ms, b_ms
+    del x, chan, inc, volt, ts, tv
+    return w, NB, n_int, f_ms, b_ms, xf
 
 
 def time_gains(torch, binding, synth, steps, device):
@@ -268,6 +297,19 @@ def time_gains(torch, binding, synth, steps, device):
     return w, n_ent, fwd, adj
 
 
+def intensity_roof(ops, nbytes, ms, peak_t):
+    """Where a contraction sits on the roofline: its arithmetic intensity (ops per algorithmic
+    HBM byte) against the ridge (MFMA peak / 8 TB/s); below the ridge HBM bounds it, and the
+    attainable MFMA fraction is intensity / ridge.  hbm_frac = the kernel's algorithmic bytes
+    per second against 8 TB/s."""
+    intensity = ops / nbytes
+    ridge = peak_t * 1e12 / (HBM_PEAK_GBS * 1e9)
+    return {"intensity_op_per_byte": round(intensity, 1), "ridge_op_per_byte": round(ridge, 1),
+            "bound_by_intensity": "hbm" if intensity < ridge else "mfma",
+            "attainable_frac": round(min(1.0, intensity / ridge), 4),
+            "hbm_frac": round(nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+
+
 def int8_leg(args, torch, binding, synth, dev, probe):
     """The 8-bit mode workload: 76 stations x 2 pol, 128 subbands of ci8 samples, int8 X stage
     (int8 MFMA, int32 sums), F then X per step as in the main leg, the streaming schedule, and
@@ -286,6 +328,7 @@ def int8_leg(args, torch, binding, synth, dev, probe):
     if not args.no_pipeline:
         step_ms = time_pipelined(torch, plan, x, delays, args.steps, args.warmup) * 1e3
     lat = block_latency(torch, plan, x, delays, max(args.steps, 60))
+    vis_bytes = plan.info["vis_bytes"]
     plan.close()
     del x
     torch.cuda.empty_cache()
@@ -308,7 +351,9 @@ def int8_leg(args, torch, binding, synth, dev, probe):
         "roofline_x": {"bound": "mfma", "achieved": round(x_tops, 1), "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
                        "frac": round(x_tops / INT8_MFMA_PEAK_TOPS, 4), "traffic": measured_traffic(x_kernel),
                        "kernel": x_kernel, "ms": round(x_s * 1e3, 4),
-                       "operand_gbs": round(w.SB * w.C * w.M * w.n_c * 2 / x_s / 1e9, 1)},
+                       "operand_gbs": round(w.SB * w.C * w.M * w.n_c * 2 / x_s / 1e9, 1),
+                       **intensity_roof(cmacs * 8, w.SB * w.C * w.M * w.n_c * 2 + vis_bytes, x_s * 1e3,
+                                        INT8_MFMA_PEAK_TOPS)},
         "roofline_f": {"bound": "alu", "achieved": round(f_tf, 1), "peak": FP32_VALU_NOPACK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(f_tf / FP32_VALU_NOPACK_TFLOPS, 4), "traffic": measured_traffic(f_kernel),
                        "kernel": f_kernel, "ms": round(f_s * 1e3, 4),
@@ -613,6 +658,8 @@ def main():
     if probe is not None and w.x_mode != synth.X_FP32:
         ref = probe["fp16_tflops"] if w.x_mode == synth.X_FP16_SPLIT else probe["int8_tops"]
         x_roof["of_mfma_probe"] = round(x_mfma_tflops / ref, 4)
+    if w.x_mode != synth.X_FP32:
+        x_roof.update(intensity_roof(x_mfma_tflops * 1e12 * x_ms_avg * 1e-3, x_bytes + info["vis_bytes"], x_ms_avg, x_peak))
     dominant = f_roof if f_ms_avg >= x_ms_avg else x_roof
     other = x_roof if dominant is f_roof else f_roof
 
@@ -639,7 +686,7 @@ def main():
 
     beam = None
     if args.beam_steps > 0:
-        bw, NB, n_int, bf_ms, bb_ms = time_beamformer(torch, binding, synth, args.beam_steps, dev)
+        bw, NB, n_int, bf_ms, bb_ms, xf = time_beamformer(torch, binding, synth, args.beam_steps, dev)
         cmac_b = bw.SB * bw.C * NB * bw.S * 2 * bw.n_c          # useful complex MACs per block
         b_ms = float(np.mean(bb_ms))
         mfma_tf = cmac_b * 8 * 3 * (128 / NB) / (b_ms * 1e-3) / 1e12     # executed: 3 products, beams padded to 128
@@ -655,6 +702,21 @@ def main():
                              "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1>"}}
         if probe is not None:
             beam["roofline"]["of_mfma_probe"] = round(mfma_tf / probe["fp16_tflops"], 4)
+        t_gbs = (xf["voltage_bytes"] + xf["stokes_bytes"]) / (xf["transform_ms"] * 1e-3) / 1e9
+        tv_gbs = 2 * xf["voltage_bytes"] / (xf["transform_voltages_ms"] * 1e-3) / 1e9
+        beam["output_resolution"] = {
+            "workload": "the same beams as complex voltages (rows of 127 beams padded to "
+                        f"{xf['stride']}), transformed from 256 to 16 channels per subband, Stokes I summed over "
+                        "16 output samples; and the same transform writing the transformed voltages",
+            "voltages_ms": round(xf["voltages_ms"], 3), "transform_ms": round(xf["transform_ms"], 3),
+            "transform_voltages_ms": round(xf["transform_voltages_ms"], 3),
+            "transform_voltages_gbs": round(tv_gbs, 1),
+            "roofline": {"bound": "hbm", "achieved": round(t_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(t_gbs / HBM_PEAK_GBS, 4), "kernel": "beam_transform_kernel<16, 1>",
+                         "traffic": measured_traffic("beam_transform_kernel<16, 1>"),
+                         "algorithmic_bytes": xf["voltage_bytes"] + xf["stokes_bytes"]}}
+        log(f"bench: beam voltages {xf['voltages_ms']:.3f} ms, transform to 16 channels {xf['transform_ms']:.3f} ms "
+            f"({t_gbs:.0f} GB/s), writing voltages {xf['transform_voltages_ms']:.3f} ms ({tv_gbs:.0f} GB/s)")
         log(f"bench: beamformer F {np.mean(bf_ms):.3f} ms + beams {b_ms:.3f} ms "
             f"({beam['beam_tcmacs']} TeraMAC/s useful, {mfma_tf:.0f} TFLOP/s executed)")
 
@@ -712,6 +774,9 @@ def main():
         "f_stage_gbs": round(f_gbs, 1),
         "roofline": dominant,
         "roofline_other": other,
+        "traffic_source": "stored, not measured in this run: HBM bytes per launch from rocprofv3 FETCH_SIZE and "
+                          "WRITE_SIZE passes (scaled by a plain copy's readings) over the same kernel sources, "
+                          "profiles/traffic.json; null where a kernel's sources changed since",
         "plain_fp32_form": fp32,
         "coarse_delay_and_flags": flagged,
         "beamformer": beam,

@@ -217,14 +217,19 @@ int cobalt_channelize_ex(cobalt_plan* plan, const void* d_in, const double* h_de
  * (the products run on matrix cores with hi/lo operands) and at most 56 stations.
  * Output layouts (float, beams fastest: each output sample is one row over the beams):
  *   d_coherent    [SB][C][N_c / n_int][n_stokes][NB]
- *   d_voltages    [SB][C][N_c][P][NB] complex (re, im)
+ *   d_voltages    [SB][C][N_c][P][NBs] complex (re, im); beams NB .. NBs-1 of a row are
+ *                 padding: unspecified on return (zeros where a kernel's beam group covers
+ *                 them, so that padded rows are written as whole lines), never read
  *   d_incoherent  [SB][C][N_c / n_int][n_stokes]
  * Any output may be NULL (not computed); at least one must be given. */
 typedef struct cobalt_beam_params {
     int32_t       n_beams;      /* NB >= 1                                                  */
     int32_t       n_stokes;     /* 1 (I) or 4 (I, Q, U, V)                                  */
     int32_t       n_int;        /* a power of two <= 32 or a multiple of 32; divides N_c    */
-    int32_t       reserved0;    /* must be 0                                                */
+    int32_t       voltage_stride; /* NBs, beams per row of d_voltages: 0 means NB, else >= NB
+                                   (at most 65536).  A multiple of 16 puts every 16 beams of
+                                   a row on whole 128-byte lines, which the output-resolution
+                                   transform reads and writes much faster              */
     const double* d_beam_dtau;  /* device [NB][S] seconds, 8-byte aligned                    */
 } cobalt_beam_params;
 
@@ -249,8 +254,9 @@ int cobalt_beamform_channelized(cobalt_plan* plan, const void* d_chan, const cob
  *     O[g][c'] = sum_m u[g c_out + m] exp(-2 pi i m (c' - c_out/2) / c_out)
  * (output channel c' ascending in frequency; c_out = 1 is the time series at the subband
  * sample rate).  Layouts (float, beams fastest), G = N_c * 256 / c_out output samples:
- *   d_voltages      [SB][256][N_c][P][NB] complex: the beamformer's voltage output
- *   d_out_voltages  [SB][G][c_out][P][NB] complex
+ *   d_voltages      [SB][256][N_c][P][NBs] complex: the beamformer's voltage output (beams
+ *                   NB .. NBs-1 of a row are padding, never read)
+ *   d_out_voltages  [SB][G][c_out][P][NBs] complex (padding beams unspecified on return)
  *   d_out_stokes    [SB][G / n_int][c_out][n_stokes][NB]: Stokes (as for the beamformer) of
  *                   the transformed voltages summed over n_int consecutive output samples */
 typedef struct cobalt_transform_params {
@@ -258,12 +264,14 @@ typedef struct cobalt_transform_params {
     int32_t c_out;       /* output channels per subband: 1, 2, 4, 8 or 16                     */
     int32_t n_stokes;    /* 1 (I) or 4 (I, Q, U, V); read only when Stokes are requested      */
     int32_t n_int;       /* a power of two up to 256 / c_out; read only when Stokes are requested */
-    int32_t reserved0;   /* must be 0                                                         */
+    int32_t voltage_stride; /* beams per row of d_voltages and d_out_voltages (NBs): 0 means NB,
+                               else >= NB; the beamformer's voltage_stride of the same voltages */
 } cobalt_transform_params;
 
 /* Transform beamformed voltages of a 256-channel plan to c_out channels; either output may
  * be NULL (not computed), not both.  Stateless (ordered by the stream alone).  Errors: EINVAL,
- * EUNSUPPORTED (plan not at 256 channels, c_out), EDEVICE. */
+ * EUNSUPPORTED (plan not at 256 channels, c_out, or one subband's voltages of 4 GiB or more:
+ * N_c * NBs must stay below 2^20), EDEVICE. */
 int cobalt_beam_transform(cobalt_plan* plan, const void* d_voltages, const cobalt_transform_params* params,
                           void* d_out_voltages, void* d_out_stokes, void* stream);
 

@@ -66,13 +66,13 @@ class BlockExt(ct.Structure):
 class BeamParams(ct.Structure):
     """``cobalt_beam_params``."""
     _fields_ = [("n_beams", ct.c_int32), ("n_stokes", ct.c_int32), ("n_int", ct.c_int32),
-                ("reserved0", ct.c_int32), ("d_beam_dtau", ct.c_void_p)]
+                ("voltage_stride", ct.c_int32), ("d_beam_dtau", ct.c_void_p)]
 
 
 class TransformParams(ct.Structure):
     """``cobalt_transform_params``."""
     _fields_ = [("n_beams", ct.c_int32), ("c_out", ct.c_int32), ("n_stokes", ct.c_int32), ("n_int", ct.c_int32),
-                ("reserved0", ct.c_int32)]
+                ("voltage_stride", ct.c_int32)]
 
 
 class ServiceStats(ct.Structure):
@@ -387,10 +387,12 @@ class Plan:
         return out
 
     # ---- beamformer --------------------------------------------------------------------
-    def beam_shapes(self, n_beams, n_stokes=4, n_int=1):
-        """Shapes of the coherent Stokes, voltage and incoherent Stokes outputs."""
+    def beam_shapes(self, n_beams, n_stokes=4, n_int=1, voltage_stride=0):
+        """Shapes of the coherent Stokes, voltage and incoherent Stokes outputs; voltage rows
+        hold ``voltage_stride`` beams (0: n_beams; 16-beam multiples are the fast layout)."""
         n_out = self.n_c // n_int
-        return ((self.SB, self.C, n_out, n_stokes, n_beams), (self.SB, self.C, self.n_c, 2, n_beams, 2),
+        nbs = voltage_stride or n_beams
+        return ((self.SB, self.C, n_out, n_stokes, n_beams), (self.SB, self.C, self.n_c, 2, nbs, 2),
                 (self.SB, self.C, n_out, n_stokes))
 
     def _beam_call(self, fn, first, delays, dtau, n_stokes, n_int, coherent, voltages, incoherent, stream):
@@ -398,8 +400,12 @@ class Plan:
         if dtau.dtype != t.float64 or dtau.dim() != 2 or dtau.shape[1] != self.S:
             raise ValueError(f"dtau: need float64 [NB][{self.S}] on the device")
         nb = dtau.shape[0]
-        cs, vs, isz = self.beam_shapes(nb, n_stokes, n_int)
-        bp = BeamParams(nb, n_stokes, n_int, 0, self._dev(dtau, tuple(dtau.shape), t.float64, "dtau"))
+        # the voltage tensor's row length is the stride (rows of 16-beam multiples are faster)
+        nbs = voltages.shape[4] if voltages is not None and voltages.dim() == 6 else nb
+        if nbs < nb:
+            raise ValueError(f"voltages: rows of {nbs} beams hold fewer than the {nb} beams")
+        cs, vs, isz = self.beam_shapes(nb, n_stokes, n_int, nbs)
+        bp = BeamParams(nb, n_stokes, n_int, nbs, self._dev(dtau, tuple(dtau.shape), t.float64, "dtau"))
         ptr = lambda x, shp, dt, name: None if x is None else self._dev(x, shp, dt, name)  # noqa: E731
         args = [self._ptr, first]
         if delays is not None:
@@ -423,21 +429,27 @@ class Plan:
                                self._dev(chan, self.chan_shape, self.chan_dtype, "chan"), None, dtau, n_stokes, n_int,
                                coherent, voltages, incoherent, stream)
 
-    def transform_shapes(self, n_beams, c_out, n_stokes=4, n_int=1):
-        """Shapes of the transformed voltages and of their Stokes (``cobalt_beam_transform``)."""
+    def transform_shapes(self, n_beams, c_out, n_stokes=4, n_int=1, voltage_stride=0):
+        """Shapes of the transformed voltages (rows of ``voltage_stride`` beams, 0: n_beams)
+        and of their Stokes (``cobalt_beam_transform``)."""
         G = self.n_c * self.C // c_out
-        return (self.SB, G, c_out, 2, n_beams, 2), (self.SB, G // n_int, c_out, n_stokes, n_beams)
+        return (self.SB, G, c_out, 2, voltage_stride or n_beams, 2), (self.SB, G // n_int, c_out, n_stokes, n_beams)
 
-    def beam_transform(self, voltages, c_out, n_stokes=4, n_int=1, out_voltages=None, out_stokes=None, stream=None):
-        """256 -> c_out channels of the beamformer's voltages (float32 [SB][256][N_c][2][NB][2]);
-        outputs are caller tensors of ``transform_shapes`` (either may be None, not both)."""
+    def beam_transform(self, voltages, c_out, n_stokes=4, n_int=1, out_voltages=None, out_stokes=None, stream=None,
+                       n_beams=None):
+        """256 -> c_out channels of the beamformer's voltages (float32 [SB][256][N_c][2][NBs][2],
+        rows of NBs beams of which the first ``n_beams`` (default NBs) are beams); outputs are
+        caller tensors of ``transform_shapes`` (either may be None, not both)."""
         t = self._torch
         if voltages.dim() != 6:
-            raise ValueError("voltages: need float32 [SB][C][N_c][2][NB][2]")
-        nb = voltages.shape[4]
-        vs = (self.SB, self.C, self.n_c, 2, nb, 2)
-        ov, osk = self.transform_shapes(nb, c_out, n_stokes, n_int)
-        tp = TransformParams(nb, c_out, n_stokes, n_int, 0)
+            raise ValueError("voltages: need float32 [SB][C][N_c][2][NBs][2]")
+        nbs = voltages.shape[4]
+        nb = nbs if n_beams is None else int(n_beams)
+        if not 1 <= nb <= nbs:
+            raise ValueError(f"n_beams must be in [1, {nbs}] (got {nb})")
+        vs = (self.SB, self.C, self.n_c, 2, nbs, 2)
+        ov, osk = self.transform_shapes(nb, c_out, n_stokes, n_int, nbs)
+        tp = TransformParams(nb, c_out, n_stokes, n_int, nbs)
         ptr = lambda x, shp, name: None if x is None else self._dev(x, shp, t.float32, name)  # noqa: E731
         _check(self._lib.cobalt_beam_transform(self._ptr, self._dev(voltages, vs, t.float32, "voltages"), ct.byref(tp),
                                                ptr(out_voltages, ov, "out_voltages"), ptr(out_stokes, osk, "out_stokes"),

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
     auto out_index = [&](int t) { return a.n_int <= kBT ? (t >> gsh) : t / a.n_int; };
     // per-channel output bases (32-bit offsets below)
     float* const co_ch = a.coherent ? (float*)a.coherent + ch * (int64_t)n_out * nS * a.NB : nullptr;
-    float2* const vo_ch = a.voltages ? (float2*)a.voltages + ch * (int64_t)a.n_c * 2 * a.NB : nullptr;
+    float2* const vo_ch = a.voltages ? (float2*)a.voltages + ch * (int64_t)a.n_c * 2 * a.vstride : nullptr;
     float* const io_ch = a.incoherent ? (float*)a.incoherent + ch * (int64_t)n_out * nS : nullptr;
     const int hb = lane >> 5;
     const int b = bt * 32 + (lane & 31);                // this lane's beam (output column)
@@ -218,14 +218,19 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                 __builtin_amdgcn_sched_barrier(0);
             }
             // register r of lane i holds sample t = 8 (r/4) + 4 (i/32) + r%4 of beam b
-            if (a.voltages && bvalid) {
+            // padding beams of a row (NB <= b < vstride) that this tile covers get zeros, so a
+            // row padded to whole 128-byte lines is written as whole lines
+            if (a.voltages && b < a.vstride) {
+                const float vs = bvalid ? vscale : 0.f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int t = tb + 8 * (r >> 2) + 4 * hb + (r & 3);
                     if (t < a.n_c) {
-                        const unsigned o = (unsigned)(t * 2 * a.NB + b);
-                        vo_ch[o] = make_float2(re[0][r] * vscale, im[0][r] * vscale);
-                        vo_ch[o + a.NB] = make_float2(re[1][r] * vscale, im[1][r] * vscale);
+                        const unsigned o = (unsigned)(t * 2 * a.vstride + b);
+                        const float x0 = bvalid ? re[0][r] : 0.f, y0 = bvalid ? im[0][r] : 0.f;
+                        const float x1 = bvalid ? re[1][r] : 0.f, y1 = bvalid ? im[1][r] : 0.f;
+                        vo_ch[o] = make_float2(x0 * vs, y0 * vs);
+                        vo_ch[o + a.vstride] = make_float2(x1 * vs, y1 * vs);
                     }
                 }
             }

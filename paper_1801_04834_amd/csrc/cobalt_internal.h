@@ -68,19 +68,21 @@ struct BeamArgs {
     const double* f_sb;      // [SB] subband sky centre frequency (Hz)
     const double* dtau;      // [NB][S] beam delay offsets (s), device
     void* coherent;          // [SB*C][N_c/n_int][n_stokes][NB] float, or null
-    void* voltages;          // [SB*C][N_c][P][NB] float (re, im), or null
+    void* voltages;          // [SB*C][N_c][P][vstride] float (re, im), or null
     void* incoherent;        // [SB*C][N_c/n_int][n_stokes] float, or null
     double df;               // channel width (Hz)
     int32_t C, S, NB, n_c, n_kb, n_chan, n_int, n_stokes;
+    int32_t vstride;         // beams per voltage row (>= NB)
     float vscale;            // 2^-k: undoes the FP16-split prescale
 };
 
 // Output-resolution transform of beamformed voltages (256 channels -> c_out channels).
 struct TfArgs {
-    const void* vin;         // [SB][256][N_c][P][NB] float (re, im): the beamformer's voltages
-    void* vout;              // [SB][N_c 256 / c_out][c_out][P][NB] float (re, im), or null
+    const void* vin;         // [SB][256][N_c][P][vstride] float (re, im): the beamformer's voltages
+    void* vout;              // [SB][N_c 256 / c_out][c_out][P][vstride] float (re, im), or null
     void* sout;              // [SB][N_c 256 / c_out / n_int][c_out][n_stokes][NB] float, or null
     int32_t SB, n_c, NB, n_bg, c_out, n_stokes, n_int;
+    int32_t vstride;         // beams per voltage row (>= NB)
 };
 
 // Launchers (return the hipError_t of the launch).

@@ -587,7 +587,8 @@ static int check_beam(const cobalt_plan* p, const cobalt_beam_params* bp, const 
     if (z.S > 56) return fail(COBALT_EUNSUPPORTED, "the beamformer supports up to 56 stations (got %lld)", (long long)z.S);
     if (bp->n_beams < 1) return fail(COBALT_EINVAL, "n_beams must be >= 1 (got %d)", bp->n_beams);
     if (bp->n_stokes != 1 && bp->n_stokes != 4) return fail(COBALT_EINVAL, "n_stokes must be 1 or 4 (got %d)", bp->n_stokes);
-    if (bp->reserved0 != 0) return fail(COBALT_EINVAL, "reserved0 must be 0");
+    if (bp->voltage_stride != 0 && (bp->voltage_stride < bp->n_beams || bp->voltage_stride > 65536))
+        return fail(COBALT_EINVAL, "voltage_stride must be 0 or in [n_beams, 65536] (got %d)", bp->voltage_stride);
     const int ni = bp->n_int;
     const bool pow2 = ni >= 1 && ni <= 32 && (ni & (ni - 1)) == 0;
     if (!(pow2 || (ni > 32 && ni % 32 == 0))) return fail(COBALT_EINVAL, "n_int must be a power of two <= 32 or a multiple of 32 (got %d)", ni);
@@ -613,6 +614,7 @@ static int run_beam(cobalt_plan* p, const void* chan, const cobalt_beam_params* 
     a.C = (int)z.C;
     a.S = (int)z.S;
     a.NB = bp->n_beams;
+    a.vstride = bp->voltage_stride ? bp->voltage_stride : bp->n_beams;
     a.n_c = (int)z.n_c;
     a.n_kb = (int)(z.pitch / kKBlock);
     a.n_chan = (int)(z.SB * z.C);
@@ -677,7 +679,9 @@ int cobalt_beam_transform(cobalt_plan* p, const void* d_voltages, const cobalt_t
     const int co = tp->c_out;
     if (co != 1 && co != 2 && co != 4 && co != 8 && co != 16)
         return fail(COBALT_EUNSUPPORTED, "c_out must be 1, 2, 4, 8 or 16 (got %d)", co);
-    if (tp->reserved0 != 0) return fail(COBALT_EINVAL, "reserved0 must be 0");
+    if (tp->voltage_stride != 0 && (tp->voltage_stride < tp->n_beams || tp->voltage_stride > 65536))
+        return fail(COBALT_EINVAL, "voltage_stride must be 0 or in [n_beams, 65536] (got %d)", tp->voltage_stride);
+    const int64_t nbs = tp->voltage_stride ? tp->voltage_stride : tp->n_beams;
     if (!d_out_voltages && !d_out_stokes) return fail(COBALT_EINVAL, "no output requested");
     if (d_out_stokes) {
         if (tp->n_stokes != 1 && tp->n_stokes != 4) return fail(COBALT_EINVAL, "n_stokes must be 1 or 4 (got %d)", tp->n_stokes);
@@ -687,8 +691,12 @@ int cobalt_beam_transform(cobalt_plan* p, const void* d_voltages, const cobalt_t
     }
     if ((!d_voltages && z.n_c > 0) || ((uintptr_t)d_voltages | (uintptr_t)d_out_voltages | (uintptr_t)d_out_stokes) % 16)
         return fail(COBALT_EINVAL, "device pointers must be non-NULL and 16-byte aligned");
-    if ((int64_t)z.SB * z.n_c * ((tp->n_beams + 15) / 16) >= ((int64_t)1 << 31))
-        return fail(COBALT_EUNSUPPORTED, "too many subbands x channel samples x beam groups for one launch");
+    if ((int64_t)z.SB * z.n_c >= ((int64_t)1 << 31))
+        return fail(COBALT_EUNSUPPORTED, "too many subbands x channel samples for one launch");
+    // the kernel addresses one subband's voltages with 32-bit byte offsets
+    if ((int64_t)256 * z.n_c * 2 * nbs * 8 >= ((int64_t)1 << 32))
+        return fail(COBALT_EUNSUPPORTED, "one subband's voltages must stay below 4 GiB (channel samples x beam stride = "
+                    "%lld, at most %lld)", (long long)(z.n_c * nbs), (long long)(((int64_t)1 << 32) / 4096) - 1);
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(COBALT_EDEVICE, "cannot select the plan's device");
     TfArgs a{};
@@ -698,6 +706,7 @@ int cobalt_beam_transform(cobalt_plan* p, const void* d_voltages, const cobalt_t
     a.SB = (int)z.SB;
     a.n_c = (int)z.n_c;
     a.NB = tp->n_beams;
+    a.vstride = (int32_t)nbs;
     a.n_bg = (tp->n_beams + 15) / 16;
     a.c_out = co;
     a.n_stokes = d_out_stokes ? tp->n_stokes : 0;

@@ -205,6 +205,51 @@ def test_output_resolution_transform_matches_oracle(c_out, n_stokes, n_int):
     assert np.all(err <= 4e-5 * np.abs(I) + 1e-6 * np.mean(np.abs(I)))
 
 
+@pytest.mark.parametrize("c_out,n_stokes,n_int", [(16, 4, 2), (4, 1, 8)])
+def test_voltage_stride_matches_packed_layout(c_out, n_stokes, n_int):
+    """Voltage rows padded to 48 beams (37 beams: the last group of 16 is partial and the row
+    is 128-byte aligned): the beamformer's voltages and the transform's outputs equal the
+    packed layout's bit for bit, and the padding beams are never read (NaN put there does not
+    reach any output)."""
+    from paper_1801_04834_amd import binding
+    S, NB, NBS, n_c, SB = 6, 37, 48, 24, 2
+    w = _work(S, SB, n_c, 3101)
+    dtau = torch.from_numpy(np.random.default_rng(3102).uniform(-4e-6, 4e-6, (NB, S))).cuda()
+    _say(f"CASE voltage stride NB={NB} stride={NBS} c_out={c_out} n_stokes={n_stokes} n_int={n_int}")
+    with binding.plan_for(w) as plan:
+        chan = plan.channelize(torch.from_numpy(w.block(0)).cuda(), w.delays(0))
+        _, vs, _ = plan.beam_shapes(NB, 4, 1)
+        _, vsp, _ = plan.beam_shapes(NB, 4, 1, voltage_stride=NBS)
+        assert vsp[4] == NBS
+        packed = torch.full(vs, np.nan, dtype=torch.float32, device="cuda")
+        padded = torch.full(vsp, np.nan, dtype=torch.float32, device="cuda")
+        plan.beamform_channelized(chan, dtau, 4, 1, voltages=packed)
+        plan.beamform_channelized(chan, dtau, 4, 1, voltages=padded)
+        torch.cuda.synchronize()
+        assert torch.equal(padded[..., :NB, :], packed)
+        padded[..., NB:, :] = float("nan")
+        ov, osk = plan.transform_shapes(NB, c_out, n_stokes, n_int)
+        ovp, _ = plan.transform_shapes(NB, c_out, n_stokes, n_int, voltage_stride=NBS)
+        tv = torch.full(ov, np.nan, dtype=torch.float32, device="cuda")
+        ts = torch.full(osk, np.nan, dtype=torch.float32, device="cuda")
+        tvp = torch.full(ovp, np.nan, dtype=torch.float32, device="cuda")
+        tsp = torch.full(osk, np.nan, dtype=torch.float32, device="cuda")
+        plan.beam_transform(packed, c_out, n_stokes, n_int, out_voltages=tv, out_stokes=ts)
+        plan.beam_transform(padded, c_out, n_stokes, n_int, out_voltages=tvp, out_stokes=tsp, n_beams=NB)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(tv).all()) and bool(torch.isfinite(ts).all())
+        assert torch.equal(tvp[..., :NB, :], tv) and torch.equal(tsp, ts)
+        # strides below the beam count are refused
+        tp = binding.TransformParams(NB, c_out, n_stokes, n_int, NB - 1)
+        rc = plan._lib.cobalt_beam_transform(plan._ptr, binding.ct.c_void_p(padded.data_ptr()), binding.ct.byref(tp),
+                                             None, binding.ct.c_void_p(tsp.data_ptr()), None)
+        assert rc == binding.EINVAL
+        bp = binding.BeamParams(NB, 4, 1, NB - 1, binding.ct.c_void_p(dtau.data_ptr()))
+        rc = plan._lib.cobalt_beamform_channelized(plan._ptr, binding.ct.c_void_p(chan.data_ptr()), binding.ct.byref(bp),
+                                                   None, binding.ct.c_void_p(padded.data_ptr()), None, None)
+        assert rc == binding.EINVAL
+
+
 def test_output_resolution_transform_rejects_bad_settings():
     from paper_1801_04834_amd import binding
     w = _work(2, 1, 16, 5)
