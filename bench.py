@@ -60,9 +60,78 @@ def measured_traffic(kernel):
             entry = json.load(fh)["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
-    if entry.get("source_sha256") != source_digest(entry["sources"]):
+    if entry.get("source_sha256") != source_digest(entry["sources"]) or "read_bytes" not in entry:
         return None
     return int(entry["read_bytes"] + entry["write_bytes"])
+
+
+KERNEL_SOURCES = (("fstage_kernel", "fstage.hip"), ("xstage_", "xstage.hip"), ("beam_transform_kernel", "beamxf.hip"),
+                  ("beam_kernel", "beam.hip"))
+
+
+def write_traffic(fetch_dir, write_dir, bench_json, copy_mib=1024):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of one command (FETCH_SIZE,
+    then WRITE_SIZE; per-dispatch values in KiB, averaged per kernel) and the bench JSON line of
+    the same sources (for each kernel's algorithmic bytes).  The plain copy kernel of the same
+    runs (copy_mib MiB read and written) calibrates both counters."""
+    import csv
+    import glob
+    import re
+
+    def per_kernel(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    m = re.search(r"(\w+_kernel(?:<[^()]*>)?)\(", row["Kernel_Name"])
+                    if m:
+                        vals.setdefault(m.group(1), []).append(float(row["Counter_Value"]))
+        return vals
+
+    fetch_d, write_d = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    fetch = {k: sum(v) / len(v) for k, v in fetch_d.items()}
+    write = {k: sum(v) / len(v) for k, v in write_d.items()}
+    # a kernel launched in more than one configuration (the beamformer with and without voltage
+    # output) has dispatches of different sizes: no single per-launch figure applies
+    mixed = {k for d in (fetch_d, write_d) for k, v in d.items() if max(v) > 1.1 * min(v) + 64}
+    with open(bench_json) as fh:
+        line = json.loads(fh.read().strip().splitlines()[-1])
+    algo = {}
+
+    def collect(o):
+        if isinstance(o, dict):
+            if "kernel" in o and o.get("algorithmic_bytes"):
+                algo[o["kernel"]] = int(o["algorithmic_bytes"])
+            for v in o.values():
+                collect(v)
+    collect(line)
+    nbytes = copy_mib * 2**20
+    cal_f, cal_w = fetch["device_copy_kernel"], write["device_copy_kernel"]
+    rf, wf = nbytes / (cal_f * 1024), nbytes / (cal_w * 1024)
+    out = {"calibration": {"kernel": "device_copy_kernel", "bytes_read": nbytes, "bytes_written": nbytes,
+                           "FETCH_SIZE_kb": round(cal_f, 1), "WRITE_SIZE_kb": round(cal_w, 1),
+                           "read_factor": round(rf, 4), "write_factor": round(wf, 4)},
+           "kernels": {}}
+    for name in sorted(set(fetch) & set(write)):
+        src = next((f for prefix, f in KERNEL_SOURCES if name.startswith(prefix)), None)
+        if src is None:
+            continue
+        files = [src, "cobalt_internal.h"]
+        if name in mixed:
+            out["kernels"][name] = {"sources": files, "source_sha256": source_digest(files),
+                                    "mixed_configurations": True}
+            continue
+        out["kernels"][name] = {
+            "sources": files, "source_sha256": source_digest(files),
+            "FETCH_SIZE_kb": round(fetch[name], 1), "WRITE_SIZE_kb": round(write[name], 1),
+            "read_bytes": int(round(fetch[name] * 1024 * rf)), "write_bytes": int(round(write[name] * 1024 * wf)),
+            "algorithmic_bytes": algo.get(name)}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    return out
 
 
 def log(msg):
@@ -100,6 +169,9 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=1024,
                     help="plain device copy of this many MiB, run three times first: the HBM rate a streaming "
                          "kernel reaches (reported as hbm_copy_gbs) and the reference for counter calibration (0: skip)")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
+                    help="no benchmark: write profiles/traffic.json from the rocprofv3 FETCH_SIZE and WRITE_SIZE "
+                         "runs of one command and the bench JSON line of the same sources")
     return ap.parse_args()
 
 
@@ -229,6 +301,7 @@ def time_beamformer(torch, binding, synth, steps, device):
     torch.cuda.synchronize()
     f_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
     b_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    cs_numel = coh.numel()
     # output resolution: the same beams as complex voltages (rows padded to 128 beams, whole
     # 128-byte lines per 16 beams), transformed to 16 channels per subband, Stokes I summed over
     # 16 output samples; then the same transform writing the transformed voltages
@@ -254,7 +327,8 @@ def time_beamformer(torch, binding, synth, steps, device):
         ev[k][3].record()
     torch.cuda.synchronize()
     beam_voltage_bytes = volt.numel() * 4 * NB // NBS        # the beams, not the padding
-    xf = {"voltages_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+    xf = {"beam_bytes": w.SB * w.C * 2 * w.S * w.n_c * 8 + (cs_numel + inc.numel()) * 4,
+          "voltages_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
           "transform_ms": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
           "transform_voltages_ms": float(np.mean([e[2].elapsed_time(e[3]) for e in ev])),
           "voltage_bytes": beam_voltage_bytes, "stokes_bytes": ts.numel() * 4, "stride": NBS}
@@ -352,12 +426,13 @@ def int8_leg(args, torch, binding, synth, dev, probe):
                        "frac": round(x_tops / INT8_MFMA_PEAK_TOPS, 4), "traffic": measured_traffic(x_kernel),
                        "kernel": x_kernel, "ms": round(x_s * 1e3, 4),
                        "operand_gbs": round(w.SB * w.C * w.M * w.n_c * 2 / x_s / 1e9, 1),
+                       "algorithmic_bytes": w.SB * w.C * w.M * w.n_c * 2 + vis_bytes,
                        **intensity_roof(cmacs * 8, w.SB * w.C * w.M * w.n_c * 2 + vis_bytes, x_s * 1e3,
                                         INT8_MFMA_PEAK_TOPS)},
         "roofline_f": {"bound": "alu", "achieved": round(f_tf, 1), "peak": FP32_VALU_NOPACK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(f_tf / FP32_VALU_NOPACK_TFLOPS, 4), "traffic": measured_traffic(f_kernel),
                        "kernel": f_kernel, "ms": round(f_s * 1e3, 4),
-                       "hbm_gbs": round(samples * 4 / f_s / 1e9, 1)},
+                       "hbm_gbs": round(samples * 4 / f_s / 1e9, 1), "algorithmic_bytes": samples * 4},
     }
     if probe is not None:
         out["roofline_x"]["of_mfma_probe"] = round(x_tops / probe["int8_tops"], 4)
@@ -526,6 +601,17 @@ def service_leg(args, torch, binding, synth):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        t = write_traffic(*args.write_traffic, copy_mib=args.copy_calibration_mib)
+        for name, e in t["kernels"].items():
+            if e.get("mixed_configurations"):
+                log(f"{name}: launched in several configurations, no per-launch figure")
+                continue
+            alg = e["algorithmic_bytes"]
+            tot = e["read_bytes"] + e["write_bytes"]
+            log(f"{name}: read {e['read_bytes'] / 1e9:.3f} GB, written {e['write_bytes'] / 1e9:.3f} GB"
+                + (f", {tot / alg:.3f} x algorithmic" if alg else ""))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only; --gpus must be 1 (the FX chain would shard over "
               "subbands with no exchange between GPUs)", file=sys.stderr)
@@ -654,7 +740,8 @@ def main():
     x_roof = {"bound": "mfma" if w.x_mode != synth.X_FP32 else "alu", "achieved": round(x_mfma_tflops, 1),
               "peak": x_peak, "unit": x_unit, "frac": round(x_mfma_tflops / x_peak, 4),
               "traffic": measured_traffic(x_kernel), "kernel": x_kernel, "ms": round(x_ms_avg, 4),
-              "operand_gbs": round(x_bytes / (x_ms_avg * 1e-3) / 1e9, 1)}
+              "operand_gbs": round(x_bytes / (x_ms_avg * 1e-3) / 1e9, 1),
+              "algorithmic_bytes": x_bytes + info["vis_bytes"]}
     if probe is not None and w.x_mode != synth.X_FP32:
         ref = probe["fp16_tflops"] if w.x_mode == synth.X_FP16_SPLIT else probe["int8_tops"]
         x_roof["of_mfma_probe"] = round(x_mfma_tflops / ref, 4)
@@ -699,7 +786,7 @@ def main():
                 "roofline": {"bound": "mfma", "achieved": round(mfma_tf, 1), "peak": FP16_MFMA_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4),
                              "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}, 1>"),
-                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1>"}}
+                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1>", "algorithmic_bytes": xf["beam_bytes"]}}
         if probe is not None:
             beam["roofline"]["of_mfma_probe"] = round(mfma_tf / probe["fp16_tflops"], 4)
         t_gbs = (xf["voltage_bytes"] + xf["stokes_bytes"]) / (xf["transform_ms"] * 1e-3) / 1e9
