@@ -51,9 +51,11 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 template <int KS, int NS>
 __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
-    // one staged block = the channelised K block as stored: [plane][row][32 samples] words,
-    // rows padded to 16 KS (8 KS stations x 2 pols; padding rows stay zero)
-    constexpr int kRows = 16 * KS;
+    // one staged block = the channelised K block with its rows regrouped by polarisation:
+    // [plane][pol][station][32 samples] words, 8 KS station rows per polarisation (padding rows
+    // stay zero), so that consecutive stations of one polarisation are consecutive rows
+    constexpr int kS8 = 8 * KS;                         // station rows per polarisation
+    constexpr int kRows = 2 * kS8;
     constexpr int kPlaneW = kRows * kBT;
     constexpr int kBuf = 2 * kPlaneW;
     __shared__ __attribute__((aligned(1024))) unsigned sm[2 * kBuf];   // double buffer
@@ -93,25 +95,29 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
     }
 
     // ---- staging: the block's rows go global -> LDS directly (global_load_lds, 16 bytes per
-    // lane, one instruction = 8 rows); the next block is requested before this block's
-    // products.  Fragments are then gathered per station row (4-byte reads). ----
+    // lane, one instruction = 8 LDS rows, each lane's source row chosen so that LDS row
+    // p kS8 + s holds global row 2 s + p); the next block is requested before this block's
+    // products.  Fragments are then gathered per station row (4-byte reads, paired). ----
     const int M = a.S * 2;
-    const int n_inst = (M + 7) / 8;                     // per plane
+    constexpr int n_inst = kRows / 8;                   // per plane
     auto issue = [&](int kb, unsigned* buf) {
         const char* blk = chan + (int64_t)kb * (2 * M * 128);
         for (int i = wv; i < 2 * n_inst; i += 4) {
             const int pl = i / n_inst, j = i % n_inst;
-            const int row = 8 * j + (lane >> 3);
-            if (row < M)
+            const int lrow = 8 * j + (lane >> 3);       // LDS row: polarisation lrow / kS8, station lrow % kS8
+            const int st = lrow % kS8, row = 2 * st + lrow / kS8;
+            if (st < a.S)
                 __builtin_amdgcn_global_load_lds((const void*)(blk + (int64_t)pl * (M * 128) + row * 128 + (lane & 7) * 16),
                                                  (lds_ptr_t)(buf + pl * kPlaneW + j * 256), 16, 0, 0);
         }
     };
-    // zero the padding rows M .. 16 KS of both planes of both buffers once
-    for (int i = tid; i < 2 * 2 * (kRows - M) * kBT; i += 256) {
-        const int bufi = i / (2 * (kRows - M) * kBT), rem = i % (2 * (kRows - M) * kBT);
-        const int pl = rem / ((kRows - M) * kBT), w = rem % ((kRows - M) * kBT);
-        sm[bufi * kBuf + pl * kPlaneW + M * kBT + w] = 0u;
+    // zero the padding rows (stations S .. kS8 - 1 of each polarisation) of both planes of both
+    // buffers once
+    const int npad = kS8 - a.S;
+    for (int i = tid; i < 2 * 2 * 2 * npad * kBT; i += 256) {
+        const int w = i % kBT, r = (i / kBT) % npad, pol = (i / (kBT * npad)) % 2, pl = (i / (kBT * npad * 2)) % 2,
+                  bufi = i / (kBT * npad * 4);
+        sm[bufi * kBuf + pl * kPlaneW + (pol * kS8 + a.S + r) * kBT + w] = 0u;
     }
     const int n_kb = a.n_kb;
     const float vscale = a.vscale;
@@ -185,14 +191,14 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                 half8 Dh[2], Dl[2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    // stations 8 ks + 4 hb + u (u = 0..3), sample lane % 32: rows 2 s + p
+                    // stations 8 ks + 4 hb + u (u = 0..3), sample lane % 32: LDS rows p kS8 + s,
+                    // read in pairs straight into the fragment's adjacent registers
                     uintx4 h, l;
+                    const int w0 = (p * kS8 + 8 * ks + 4 * hb) * kBT + (lane & 31);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int w = (2 * (8 * ks + 4 * hb + u) + p) * kBT + (lane & 31);
-                        h[u] = buf[w];
-                        l[u] = buf[kPlaneW + w];
-                    }
+                    for (int u = 0; u < 4; ++u) h[u] = buf[w0 + u * kBT];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) l[u] = buf[kPlaneW + w0 + u * kBT];
                     Dh[p] = __builtin_bit_cast(half8, h);
                     Dl[p] = __builtin_bit_cast(half8, l);
                 }
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
                 float v[2][2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    const unsigned hw = buf[(2 * s + p) * kBT + tl], lw = buf[kPlaneW + (2 * s + p) * kBT + tl];
+                    const unsigned hw = buf[(p * kS8 + s) * kBT + tl], lw = buf[kPlaneW + (p * kS8 + s) * kBT + tl];
                     // hi + lo of the (re, im) halves in one mixed-precision FMA each (exact in FP32)
                     asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(v[p][0]) : "v"(hw), "v"(lw));
                     asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(v[p][1]) : "v"(hw), "v"(lw));
