@@ -38,19 +38,26 @@ __device__ __forceinline__ void split_h2(float a, float b, unsigned& hi, unsigne
     lo = __builtin_bit_cast(unsigned, l);
 }
 
-// (a, b) -> (-b, a) on packed fp16 pairs: (Re w, -Im w) -> (Im w, Re w).  Exact for both the
-// hi and the lo part of the split (a sign flip and a move).
+// (a, b) -> (-b, a) on packed fp16 pairs: (Re w, -Im w) -> (Im w, Re w).  One packed max of a
+// register with itself, the low result taking the negated high half and the high result the low
+// half: exact for both the hi and the lo part of the split (fp16 denormals are kept).
 __device__ __forceinline__ uintx4 re_to_im(uintx4 d) {
     uintx4 r;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = __builtin_amdgcn_alignbit(d[e], d[e], 16) ^ 0x00008000u;
+    for (int e = 0; e < 4; ++e)
+        asm("v_pk_max_f16 %0, %1, %1 op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[1,1]" : "=v"(r[e]) : "v"(d[e]));
     return r;
 }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
+// Waves per SIMD the register budget is set for: three workgroups per CU where the LDS (two
+// staged blocks of 16 KS rows) and the registers of up to 48 stations allow it.
+template <int KS>
+constexpr int beam_waves() { return KS <= 6 ? 3 : 2; }
+
 template <int KS, int NS>
-__global__ __launch_bounds__(256, 2) void beam_kernel(BeamArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<KS>()))) void beam_kernel(BeamArgs a) {
     // one staged block = the channelised K block with its rows regrouped by polarisation:
     // [plane][pol][station][32 samples] words, 8 KS station rows per polarisation (padding rows
     // stay zero), so that consecutive stations of one polarisation are consecutive rows
