@@ -255,8 +255,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
                 const int per = g >= 8 ? g / 8 : 1;
                 const bool full = tb + kBT <= a.n_c;            // no sample past N_c (uniform)
                 float part[NS] = {};
+                // Stokes I over windows of 8 or more samples in a whole block: the squares go
+                // straight into the window sum, four FMAs per sample, nothing to mask
+                const bool fast = NS == 1 && g >= 8 && full;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 4 && fast; ++q) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int r = 4 * q + u;
+                        part[0] = fmaf(re[0][r], re[0][r], part[0]);
+                        part[0] = fmaf(im[0][r], im[0][r], part[0]);
+                        part[0] = fmaf(re[1][r], re[1][r], part[0]);
+                        part[0] = fmaf(im[1][r], im[1][r], part[0]);
+                    }
+                    if ((q + 1) % per == 0) {
+                        const int t = tb + 8 * (q + 1 - per);
+                        const float v = add_halves(part[0]) * sscale;
+                        if (hb == 0 && bvalid) put(co_ch + (unsigned)(out_index(t) * a.NB + b), t, v);
+                        part[0] = 0.f;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4 && !fast; ++q) {
                     float st[4][NS];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -314,10 +334,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
                     asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(v[p][0]) : "v"(hw), "v"(lw));
                     asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(v[p][1]) : "v"(hw), "v"(lw));
                 }
-                float st4[NS];
-                stokes(v[0][0], v[0][1], v[1][0], v[1][1], st4);
+                if constexpr (NS == 1) {
+                    acc[0] = fmaf(v[0][0], v[0][0], acc[0]);
+                    acc[0] = fmaf(v[0][1], v[0][1], acc[0]);
+                    acc[0] = fmaf(v[1][0], v[1][0], acc[0]);
+                    acc[0] = fmaf(v[1][1], v[1][1], acc[0]);
+                } else {
+                    float st4[NS];
+                    stokes(v[0][0], v[0][1], v[1][0], v[1][1], st4);
 #pragma unroll
-                for (int k = 0; k < NS; ++k) acc[k] += st4[k];
+                    for (int k = 0; k < NS; ++k) acc[k] += st4[k];
+                }
             }
             const int t = tb + tl;
 #pragma unroll
