@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kXThreads, 4) void beam_transform_kernel(TfArgs a) 
             for (int n1 = 0; n1 < 16; ++n1) {
                 const int i = bitrev<16>(n1);
                 if constexpr (NS == 1) {
-                    acc[0] += xr[i] * xr[i] + xi[i] * xi[i];
+                    acc[0] = fmaf(xr[i], xr[i], acc[0]);
+                    acc[0] = fmaf(xi[i], xi[i], acc[0]);
                 } else {
                     const auto sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(xr[i]), __float_as_uint(xr[i]), false, false);
                     const auto si = __builtin_amdgcn_permlane16_swap(__float_as_uint(xi[i]), __float_as_uint(xi[i]), false, false);
