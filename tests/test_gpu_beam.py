@@ -63,7 +63,8 @@ def _check(label, coh, volt, inc, o):
 
 
 @pytest.mark.parametrize("S,NB,n_c,n_int,n_stokes", [(6, 37, 40, 1, 4), (6, 37, 40, 8, 4), (13, 130, 64, 64, 1),
-                                                     (48, 32, 96, 32, 4), (1, 1, 33, 1, 4), (56, 40, 32, 16, 1)])
+                                                     (48, 32, 96, 32, 4), (1, 1, 33, 1, 4), (56, 40, 32, 16, 1),
+                                                     (48, 127, 96, 16, 1), (20, 70, 96, 8, 1)])
 def test_beamformer_matches_oracle(S, NB, n_c, n_int, n_stokes):
     from paper_1801_04834_amd import binding
     SB = 2
@@ -83,13 +84,43 @@ def test_beamformer_matches_oracle(S, NB, n_c, n_int, n_stokes):
             volt = torch.full(vs, np.nan, dtype=torch.float32, device="cuda")
             inc = torch.full(isz, np.nan, dtype=torch.float32, device="cuda")
             plan.beamform(x, w.delays(k), dt, n_stokes, n_int, coherent=coh, voltages=volt, incoherent=inc)
-            # the same block through the F stage + the stateless beamformer on a second plan
+            # the same block through the F stage + the stateless beamformer on a second plan,
+            # without voltage output (for Stokes I over 8 or more samples and N_c a multiple of
+            # 32 that is the kernel form interleaving the Stokes sums with the products): the
+            # same bits
             chan = plan2.channelize(x, w.delays(k))
             coh2 = torch.full(cs, np.nan, dtype=torch.float32, device="cuda")
-            plan2.beamform_channelized(chan, dt, n_stokes, n_int, coherent=coh2)
+            inc2 = torch.full(isz, np.nan, dtype=torch.float32, device="cuda")
+            plan2.beamform_channelized(chan, dt, n_stokes, n_int, coherent=coh2, incoherent=inc2)
             torch.cuda.synchronize()
             assert torch.equal(coh, coh2)
+            assert torch.equal(inc, inc2)
             _check(f"block {k}", coh.cpu().numpy(), volt.cpu().numpy(), inc.cpu().numpy(), outs[k])
+
+
+@pytest.mark.parametrize("n_int", [8, 16])
+def test_incoherent_only_and_coherent_only_match_the_full_call(n_int):
+    """Stokes I over 8 or more samples without voltages (the interleaved kernel form): asking for
+    the incoherent beam alone, or the coherent beams alone, gives the same bits as asking for
+    both, and nothing is written through the output that is not asked for."""
+    from paper_1801_04834_amd import binding
+    S, NB, n_c = 20, 70, 64
+    w = _work(S, 2, n_c, 3301 + n_int)
+    dt = torch.from_numpy(np.random.default_rng(3302).uniform(-4e-6, 4e-6, (NB, S))).cuda()
+    _say(f"CASE beam incoherent-only / coherent-only S={S} NB={NB} n_c={n_c} n_int={n_int}")
+    with binding.plan_for(w) as plan:
+        chan = plan.channelize(torch.from_numpy(w.block(0)).cuda(), w.delays(0))
+        cs, _, isz = plan.beam_shapes(NB, 1, n_int)
+        coh = torch.full(cs, np.nan, dtype=torch.float32, device="cuda")
+        inc = torch.full(isz, np.nan, dtype=torch.float32, device="cuda")
+        plan.beamform_channelized(chan, dt, 1, n_int, coherent=coh, incoherent=inc)
+        inc1 = torch.full(isz, np.nan, dtype=torch.float32, device="cuda")
+        plan.beamform_channelized(chan, dt, 1, n_int, incoherent=inc1)
+        coh1 = torch.full(cs, np.nan, dtype=torch.float32, device="cuda")
+        plan.beamform_channelized(chan, dt, 1, n_int, coherent=coh1)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(coh).all()) and bool(torch.isfinite(inc).all())
+        assert torch.equal(inc1, inc) and torch.equal(coh1, coh)
 
 
 def test_pointed_beam_on_a_tone():
