@@ -24,12 +24,13 @@
 //
 // Work decomposition: one workgroup of 512 threads per (subband, channel sample): 16 digits x
 // 32 transforms (2 polarisations x 16 beams, the transform index fastest in a wavefront, so a
-// load instruction reads 128-byte runs of beams).  The workgroup walks the groups of 16 beams
-// of its row, loading the next group into registers while it transforms the current one; the
-// twiddles stay in registers for the whole row.  Stokes parameters at C_out = 16 are summed in
-// registers (the output channel is the thread's digit, the polarisations sit 16 lanes apart);
-// at other C_out the outputs go through LDS to be summed across threads.  Memory-bound: one
-// read of the voltages, one write of the outputs.
+// load instruction reads 128-byte runs of beams; rows padded to whole 128-byte lines keep
+// every such run on one line).  The workgroup walks the groups of 16 beams of its row, loading
+// the next group into registers while it transforms the current one; the twiddles come from a
+// 2 KB LDS table.  Stokes parameters at C_out = 16 are summed in registers (the output channel
+// is the thread's digit, the polarisations sit 16 lanes apart); at other C_out the outputs go
+// through LDS to be summed across threads.  Memory-bound: one read of the voltages, one write
+// of the outputs.
 #include "cobalt_internal.h"
 
 namespace cobalt {
