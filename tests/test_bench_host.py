@@ -37,3 +37,44 @@ def test_traffic_entries_match_their_sources():
         else:
             assert got is None
     assert bench.measured_traffic("no_such_kernel") is None
+
+
+def _counter_csv(path, counter, rows):
+    """A rocprofv3 counter_collection.csv with the columns the traffic writer reads."""
+    import csv
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "pmc_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (name, value) in enumerate(rows):
+            w.writerow([i, name, counter, value])
+
+
+def test_write_traffic_calibrates_and_flags_mixed_launches(tmp_path, monkeypatch):
+    """The counter summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged per kernel) scaled
+    by what the plain copy of 1 GiB reads; algorithmic bytes taken from the bench line; a kernel
+    whose dispatches differ in size is marked mixed and reports no traffic."""
+    f_dir, w_dir = str(tmp_path / "F"), str(tmp_path / "W")
+    copy = "cobalt::(anonymous namespace)::device_copy_kernel(uint4*, uint4 const*, long)"
+    fst = "void cobalt::(anonymous namespace)::fstage_kernel<2, 1, 64>(cobalt::FArgs)"
+    beam = "void cobalt::(anonymous namespace)::beam_kernel<6, 1>(cobalt::BeamArgs)"
+    _counter_csv(f_dir, "FETCH_SIZE", [(copy, 524288.0), (fst, 1000.0), (fst, 1000.0), (beam, 100.0), (beam, 300.0)])
+    _counter_csv(w_dir, "WRITE_SIZE", [(copy, 1048576.0), (fst, 3000.0), (fst, 3000.0), (beam, 10.0), (beam, 10.0)])
+    line = {"roofline": {"kernel": "fstage_kernel<2, 1, 64>", "algorithmic_bytes": 6000 * 1024},
+            "beamformer": {"roofline": {"kernel": "beam_kernel<6, 1>", "algorithmic_bytes": 1}}}
+    bj = tmp_path / "bench.json"
+    bj.write_text("bench: a log line\n" + json.dumps(line) + "\n")
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    t = bench.write_traffic(f_dir, w_dir, str(bj))
+    cal = t["calibration"]
+    assert cal["read_factor"] == 2.0 and cal["write_factor"] == 1.0
+    e = t["kernels"]["fstage_kernel<2, 1, 64>"]
+    assert e["read_bytes"] == 2 * 1000 * 1024 and e["write_bytes"] == 3000 * 1024
+    assert e["algorithmic_bytes"] == 6000 * 1024
+    assert e["source_sha256"] == bench.source_digest(e["sources"])
+    assert t["kernels"]["beam_kernel<6, 1>"].get("mixed_configurations")
+    assert "device_copy_kernel" not in t["kernels"]
+    assert json.loads(out.read_text()) == t
+    assert bench.measured_traffic("fstage_kernel<2, 1, 64>") == 5000 * 1024
+    assert bench.measured_traffic("beam_kernel<6, 1>") is None
