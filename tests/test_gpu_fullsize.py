@@ -162,3 +162,46 @@ def test_full_size_beamformer_on_sampled_subbands():
         worst = float(np.max(err / (np.abs(want) + np.mean(np.abs(want)))))
         _say(f"  {name}: worst {worst:.3e}")
         assert np.all(err <= 2e-5 * np.abs(want) + 1e-6 * np.mean(np.abs(want))), f"{name} off, worst {worst:.3e}"
+
+
+def test_full_size_output_resolution_on_sampled_rows():
+    """The output-resolution transform at the benchmark's size and launch configuration (61
+    subbands x 768 channel samples, 127 beams in rows padded to 128, 256 -> 16 channels, Stokes I
+    over 16 output samples, and the transformed voltages): sampled (subband, channel sample)
+    rows against the oracle's transform of the same voltages, row by row (FP32 transform error
+    only: voltages <= 2e-6 of the rms, Stokes |dS| <= 4e-5 I + 1e-6 mean(I))."""
+    from paper_1801_04834_amd import binding
+    from oracle import beam as obeam
+    w = synth.Workload(name="beam_share", S=48, SB=61, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, C=256,
+                       sigma=64.0, seed=1807, fp16_prescale_log2=-1)
+    NB, NBS, c_out, n_int = 127, 128, 16, 16
+    rng = np.random.default_rng(4101)
+    rows = [(int(rng.integers(w.SB)), int(rng.integers(w.n_c))) for _ in range(6)] + [(0, 0), (w.SB - 1, w.n_c - 1)]
+    _say(f"CASE fullsize transform SB={w.SB} n_c={w.n_c} NB={NB} stride={NBS} c_out={c_out} n_int={n_int} rows={rows}")
+    with binding.plan_for(w) as plan:
+        _, vs, _ = plan.beam_shapes(NB, 1, 1, voltage_stride=NBS)
+        g = torch.Generator(device="cuda").manual_seed(4102)
+        volt = torch.randn(vs, generator=g, dtype=torch.float32, device="cuda")
+        ov, osk = plan.transform_shapes(NB, c_out, 1, n_int, voltage_stride=NBS)
+        tv = torch.full(ov, np.nan, dtype=torch.float32, device="cuda")
+        ts = torch.full(osk, np.nan, dtype=torch.float32, device="cuda")
+        plan.beam_transform(volt, c_out, 1, n_int, out_voltages=tv, out_stokes=ts, n_beams=NB)
+        torch.cuda.synchronize()
+        per = w.C // c_out                           # output samples per channel sample
+        for sb, j in rows:
+            v = volt[sb, :, j, :, :NB].cpu().numpy().astype(np.float64)           # [C, P, NB, 2]
+            B = np.transpose(v[..., 0] + 1j * v[..., 1], (2, 1, 0))[..., None]    # [NB, P, C, 1]
+            ref = obeam.resolution_transform(B, c_out)                            # [NB, P, per, c_out]
+            got = tv[sb, j * per:(j + 1) * per, :, :, :NB].cpu().numpy().astype(np.float64)
+            got = np.transpose(got[..., 0] + 1j * got[..., 1], (3, 2, 0, 1))      # [NB, P, per, c_out]
+            rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+            e = float(np.max(np.abs(got - ref))) / rms
+            st = obeam.transformed_stokes(B, c_out, "I", n_int)                   # [NB, per/n_int, c_out, 1]
+            sg = ts[sb, j * per // n_int:(j + 1) * per // n_int].cpu().numpy().astype(np.float64)
+            sg = np.transpose(sg, (3, 0, 1, 2))                                   # [NB, per/n_int, c_out, 1]
+            err = np.abs(sg - st)
+            worst = float(np.max(err / (np.abs(st) + np.mean(np.abs(st)))))
+            _say(f"  row (sb {sb}, j {j}): voltages {e:.2e} rms, Stokes worst {worst:.2e}")
+            assert e <= 2e-6
+            assert np.all(err <= 4e-5 * np.abs(st) + 1e-6 * np.mean(np.abs(st)))
+        assert bool(torch.isfinite(ts).all())
