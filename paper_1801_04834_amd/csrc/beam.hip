@@ -227,8 +227,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
                     re[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[p], Wl_re, re[p], 0, 0, 0);
                     im[p] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[p], Wl_im, im[p], 0, 0, 0);
                 }
-                // keep each k-step's fragments local (two workgroups per CU hide the LDS latency)
-                __builtin_amdgcn_sched_barrier(0);
             }
             // register r of lane i holds sample t = 8 (r/4) + 4 (i/32) + r%4 of beam b
             // padding beams of a row (NB <= b < vstride) that this tile covers get zeros, so a
