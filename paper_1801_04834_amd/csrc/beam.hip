@@ -107,16 +107,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
     // products.  Fragments are then gathered per station row (4-byte reads, paired). ----
     const int M = a.S * 2;
     constexpr int n_inst = kRows / 8;                   // per plane
+    // Eight LDS rows of one instruction are 8 consecutive stations of one polarisation (8 divides
+    // kS8), i.e. global rows 2 (st0 + l) + pol, l = lane / 8: the lane's part of the source
+    // offset is the same for every instruction and the rest is wave-uniform.
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    const int lst = lane >> 3;
+    const unsigned lane_off = (unsigned)(lst * 256 + (lane & 7) * 16);
+    constexpr int kIt = (2 * n_inst + 3) / 4;           // instructions per wave and block
+    int src_off[kIt], dst_off[kIt];                     // wave-uniform, fixed for the kernel
+    bool live[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int i = wvu + 4 * it;
+        const int pl = i / n_inst, j = i % n_inst;
+        const int pol = (8 * j) / kS8, st0 = (8 * j) % kS8;
+        src_off[it] = (pl * M + 2 * st0 + pol) * 128;
+        dst_off[it] = pl * kPlaneW + j * 256;
+        live[it] = i < 2 * n_inst && st0 + lst < a.S;
+    }
     auto issue = [&](int kb, unsigned* buf) {
         const char* blk = chan + (int64_t)kb * (2 * M * 128);
-        for (int i = wv; i < 2 * n_inst; i += 4) {
-            const int pl = i / n_inst, j = i % n_inst;
-            const int lrow = 8 * j + (lane >> 3);       // LDS row: polarisation lrow / kS8, station lrow % kS8
-            const int st = lrow % kS8, row = 2 * st + lrow / kS8;
-            if (st < a.S)
-                __builtin_amdgcn_global_load_lds((const void*)(blk + (int64_t)pl * (M * 128) + row * 128 + (lane & 7) * 16),
-                                                 (lds_ptr_t)(buf + pl * kPlaneW + j * 256), 16, 0, 0);
-        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it)
+            if (live[it])
+                __builtin_amdgcn_global_load_lds((const void*)(blk + src_off[it] + lane_off),
+                                                 (lds_ptr_t)(buf + dst_off[it]), 16, 0, 0);
     };
     // zero the padding rows (stations S .. kS8 - 1 of each polarisation) of both planes of both
     // buffers once
@@ -143,7 +158,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
     const int b = bt * 32 + (lane & 31);                // this lane's beam (output column)
     const bool bvalid = b < a.NB;
 
-    // Stokes of one (beam, sample) from the two polarisations' voltages
     // Stokes of one (beam, sample) from the two polarisations' voltages (unscaled)
     auto stokes = [&](float xr, float xi, float yr, float yi, float* st) {
         const float xx = xr * xr + xi * xi, yy = yr * yr + yi * yi;
@@ -164,15 +178,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
         if (a.n_int <= kBT || tstart % a.n_int == 0) *o = v;
         else *o += v;
     };
-    // incoherent per-sample sums of a block, [buffer][sample][stokes], for windows > 8 samples
-    __shared__ float inc_t[2][kBT][4];
-    auto inc_finish = [&](int kbp) {                    // wave 0, after a barrier
-        if (wv != 0 || lane >= (kBT / g) * nS) return;
-        const int grp = lane / nS, k = lane % nS, tb0 = kbp * kBT + grp * g;
-        if (tb0 >= a.n_c) return;
-        float v = 0.f;
-        for (int u = 0; u < g; ++u) v += inc_t[kbp & 1][grp * g + u][k];
-        put(io_ch + out_index(tb0) * nS + k, tb0, v);
+    // incoherent partial sums of a block, [buffer][wave][sample][stokes]: wave w holds the sums
+    // over the stations of groups 2w and 2w + 1 (station s is in group s % 8)
+    __shared__ float inc_p[2][4][kBT][NS];
+    // after a barrier: the four partial sums of each sample of block kbp in a fixed order, then
+    // the sums over windows of g samples (lanes (stokes, sample) of waves 0 .. NS/2)
+    auto inc_finish = [&](int kbp) {
+        const int idx = wv * 64 + lane, k = idx / kBT, tl = idx % kBT;
+        if (k >= NS) return;
+        const int t = kbp * kBT + tl;
+        const int bi = kbp & 1;
+        float x = t < a.n_c ? ((inc_p[bi][0][tl][k] + inc_p[bi][1][tl][k]) + (inc_p[bi][2][tl][k] + inc_p[bi][3][tl][k])) * sscale : 0.f;
+        for (int m = 1; m < g; m <<= 1) x += __shfl_xor(x, m, 64);
+        if ((tl & (g - 1)) == 0 && t < a.n_c) put(io_ch + out_index(t) * nS + k, t, x);
     };
 
     __syncthreads();
@@ -181,12 +199,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
         unsigned* buf = sm + (kb & 1) * kBuf;
         __builtin_amdgcn_s_waitcnt(0);                  // this wave's transfers of block kb have landed
         __syncthreads();                                // ... and everyone's; buffer kb+1 is free
-        if (do_inc && g > 8 && kb > 0) inc_finish(kb - 1);
+        if (do_inc && kb > 0) inc_finish(kb - 1);
         if (kb + 1 < n_kb) issue(kb + 1, sm + ((kb + 1) & 1) * kBuf);
         const int tb = kb * kBT;
 
         // ---- coherent: D[t][b] = data (32 samples x K) . weights (K x 32 beams) ----
-        if (bt * 32 < a.NB) {
+        if ((a.coherent || a.voltages) && bt * 32 < a.NB) {
             floatx16 re[2], im[2];
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
@@ -319,11 +337,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
             }
         }
 
-        // ---- incoherent: wave w sums samples 8w .. 8w+7; lane = (station group, sample) ----
+        // ---- incoherent: lane (half hb, sample tl) of wave w sums stations 8 ks + 2 w + hb; one
+        // read of a wave covers two station rows of 32 samples ----
         if (do_inc) {
-            const int tl = 8 * wv + (lane & 7), grp = lane >> 3;
+            const int tl = lane & 31, grp = 2 * wv + hb;
             float acc[NS] = {};
-            for (int s = grp; s < a.S; s += 8) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int s = grp + 8 * ks;
+                if (s >= a.S) continue;
                 float v[2][2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
@@ -344,24 +366,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
                     for (int k = 0; k < NS; ++k) acc[k] += st4[k];
                 }
             }
-            const int t = tb + tl;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                float x = t < a.n_c ? acc[k] * sscale : 0.f;
-                x += __shfl_xor(x, 8, 64);
-                x += __shfl_xor(x, 16, 64);
-                x += __shfl_xor(x, 32, 64);              // every lane: the sum over station groups
-                if (g <= 8) {
-                    for (int m = 1; m < g; m <<= 1) x += __shfl_xor(x, m, 64);
-                    if (grp == 0 && (tl % g) == 0 && t < a.n_c)
-                        io_ch[out_index(t) * nS + k] = x;
-                } else if (grp == 0) {
-                    inc_t[kb & 1][tl][k] = x;
-                }
+                const float x = add_halves(acc[k]);
+                if (hb == 0) inc_p[kb & 1][wv][tl][k] = x;
             }
         }
     }
-    if (do_inc && g > 8 && n_kb > 0) {
+    if (do_inc && n_kb > 0) {
         __syncthreads();
         inc_finish(n_kb - 1);
     }
