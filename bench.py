@@ -454,15 +454,20 @@ def block_latency(torch, plan, x, delays, n):
     return np.array(out)
 
 
+def oracle_threads():
+    """Threads the oracle's BLAS uses on this host."""
+    try:
+        import threadpoolctl
+        return int(max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1)
+    except Exception:
+        return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(w, n_sub):
     """The FP64 oracle on n_sub subbands of the same workload, on this host's cores."""
     import oracle
     from paper_1801_04834_amd import synth
-    try:
-        import threadpoolctl
-        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
-    except Exception:
-        threads = len(os.sched_getaffinity(0))
+    threads = oracle_threads()
     sbs = list(range(n_sub))
     x = synth.to_complex(w.block(0, subbands=sbs))
     hist = np.zeros((w.S, 2, n_sub, 960), np.complex128)
@@ -477,6 +482,56 @@ def cpu_baseline(w, n_sub):
                       f"{dt:.2f} s per sample, real-time factor {w.N / 195312.5 * n_sub / w.SB / dt:.4f} "
                       f"for the whole block",
             "seconds": dt}
+
+
+def beam_cpu_baselines(bw, NB, n_int, n_sub=1, n_tb=16):
+    """The FP64 beamformer oracle on n_sub subbands of the beamformer workload (F stage at 256
+    channels, coherent beams, Stokes I over n_int samples, incoherent I), then its
+    output-resolution transform (256 -> 16 channels, Stokes I over 16 output samples) on n_tb of
+    those beams.  Returns the two baselines."""
+    from oracle import beam as ob
+    from paper_1801_04834_amd import synth
+    threads = oracle_threads()
+    sbs = list(range(n_sub))
+    x = synth.to_complex(bw.block(0, subbands=sbs))
+    hist = np.zeros((bw.S, 2, n_sub, (bw.T - 1) * bw.C), np.complex128)
+    dtau = np.random.default_rng(1808).uniform(-2e-6, 2e-6, (NB, bw.S))
+    t0 = time.perf_counter()
+    r = ob.beamform_block(x, hist, bw.fir(), bw.bandpass(), bw.subband_freqs()[:n_sub], synth.SAMPLE_RATE_HZ,
+                          bw.delays(0), dtau, bw.C, bw.T, which="I", n_int=n_int)
+    dt_b = time.perf_counter() - t0
+    cmacs = n_sub * bw.C * NB * bw.S * 2 * bw.n_c
+    B = np.moveaxis(r["beams"][0][:, :n_tb], 0, -2)          # [beam, P, C, N_c]
+    t0 = time.perf_counter()
+    ob.transformed_stokes(B, 16, "I", 16)
+    dt_t = time.perf_counter() - t0
+    vbytes = B.size * 8                                     # complex64 voltages consumed
+    beam = {"value": cmacs / dt_b / 1e12, "unit": "TeraMAC/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_sub} of {bw.SB} subbands (all {bw.S} stations, {NB} beams, N={bw.N}), F stage at "
+                      f"{bw.C} channels included; {dt_b:.2f} s", "seconds": dt_b}
+    xf = {"value": vbytes / dt_t / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+          "sample": f"{n_tb} of {NB} beams of 1 subband ({vbytes / 1e6:.0f} MB of voltages); {dt_t:.2f} s",
+          "seconds": dt_t}
+    return beam, xf
+
+
+def gains_cpu_baseline(gw):
+    """The FP64 gains oracle (forward and adjoint) on the whole gains workload: random
+    visibilities, gains and upstream gradient of the same shapes.  GB/s of visibility entries
+    (16 B per complex entry) through the forward and the adjoint together."""
+    from oracle import gains as og
+    rng = np.random.default_rng(1811)
+    B = gw.S * (gw.S + 1) // 2
+    shp = (gw.SB, gw.C, B, 4)
+    V0 = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    G = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    g = np.exp(1j * rng.uniform(-np.pi, np.pi, (gw.SB, gw.C, gw.M)))
+    t0 = time.perf_counter()
+    og.apply_gains(V0, g, gw.S)
+    og.apply_gains_adjoint(V0, g, G, gw.S)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * V0.size * 16 / dt / 1e9, "unit": "GB/s", "cores": oracle_threads(), "kind": "oracle",
+            "sample": f"the whole workload ({V0.size} entries), forward and adjoint; {dt:.2f} s", "seconds": dt}
 
 
 def service_workloads(synth):
@@ -815,6 +870,16 @@ def main():
                  "forward_gbs": round(n_ent * 16 / (fwd * 1e-3) / 1e9, 1),
                  "adjoint_gbs": round(n_ent * 16 / (adj * 1e-3) / 1e9, 1)}
         log(f"bench: gains forward {fwd:.3f} ms, adjoint {adj:.3f} ms ({n_ent} visibility entries)")
+
+    if beam is not None and not args.no_cpu_baseline:
+        log("bench: beamformer and output-resolution oracles for their CPU baselines")
+        beam["cpu_baseline"], beam["output_resolution"]["cpu_baseline"] = beam_cpu_baselines(bw, NB, n_int)
+        log(f"bench: beamformer oracle {beam['cpu_baseline']['seconds']:.2f} s, transform oracle "
+            f"{beam['output_resolution']['cpu_baseline']['seconds']:.2f} s")
+
+    if gains is not None and not args.no_cpu_baseline:
+        gains["cpu_baseline"] = gains_cpu_baseline(gw)
+        log(f"bench: gains oracle {gains['cpu_baseline']['seconds']:.2f} s")
 
     cpu = None
     if not args.no_cpu_baseline:
