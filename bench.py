@@ -840,8 +840,8 @@ def main():
                 "real_time_factor": round(bw.N / synth.SAMPLE_RATE_HZ / ((float(np.mean(bf_ms)) + b_ms) * 1e-3), 2),
                 "roofline": {"bound": "mfma", "achieved": round(mfma_tf, 1), "peak": FP16_MFMA_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(mfma_tf / FP16_MFMA_PEAK_TFLOPS, 4),
-                             "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}, 1>"),
-                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1>", "algorithmic_bytes": xf["beam_bytes"]}}
+                             "traffic": measured_traffic(f"beam_kernel<{(bw.S + 7) // 8}, 1, false>"),
+                             "kernel": f"beam_kernel<{(bw.S + 7) // 8}, 1, false>", "algorithmic_bytes": xf["beam_bytes"]}}
         if probe is not None:
             beam["roofline"]["of_mfma_probe"] = round(mfma_tf / probe["fp16_tflops"], 4)
         t_gbs = (xf["voltage_bytes"] + xf["stokes_bytes"]) / (xf["transform_ms"] * 1e-3) / 1e9

@@ -56,7 +56,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 template <int KS>
 constexpr int beam_waves() { return KS <= 6 ? 3 : 2; }
 
-template <int KS, int NS>
+template <int KS, int NS, bool VOLT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<KS>()))) void beam_kernel(BeamArgs a) {
     // one staged block = the channelised K block with its rows regrouped by polarisation:
     // [plane][pol][station][32 samples] words, 8 KS station rows per polarisation (padding rows
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
         const int tb = kb * kBT;
 
         // ---- coherent: D[t][b] = data (32 samples x K) . weights (K x 32 beams) ----
-        if ((a.coherent || a.voltages) && bt * 32 < a.NB) {
+        if ((VOLT || a.coherent) && bt * 32 < a.NB) {
             floatx16 re[2], im[2];
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
             // register r of lane i holds sample t = 8 (r/4) + 4 (i/32) + r%4 of beam b
             // padding beams of a row (NB <= b < vstride) that this tile covers get zeros, so a
             // row padded to whole 128-byte lines is written as whole lines
-            if (a.voltages && b < a.vstride) {
+            if (VOLT && b < a.vstride) {
                 const float vs = bvalid ? vscale : 0.f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
@@ -379,13 +379,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
     }
 }
 
+// VOLT: the voltage output is compiled in only where voltages are asked for
 template <int KS>
 hipError_t launch_ks(const BeamArgs& a, hipStream_t st) {
     const dim3 grid((unsigned)a.n_chan, (unsigned)((a.NB + 127) / 128)), block(256);
-    if (a.n_stokes == 1)
-        hipLaunchKernelGGL((beam_kernel<KS, 1>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((beam_kernel<KS, 4>), grid, block, 0, st, a);
+    const bool v = a.voltages != nullptr;
+    if (a.n_stokes == 1) {
+        if (v) hipLaunchKernelGGL((beam_kernel<KS, 1, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((beam_kernel<KS, 1, false>), grid, block, 0, st, a);
+    } else {
+        if (v) hipLaunchKernelGGL((beam_kernel<KS, 4, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((beam_kernel<KS, 4, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 
