@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
     // over the stations of groups 2w and 2w + 1 (station s is in group s % 8)
     __shared__ float inc_p[2][4][kBT][NS];
     // after a barrier: the four partial sums of each sample of block kbp in a fixed order, then
-    // the sums over windows of g samples (lanes (stokes, sample) of waves 0 .. NS/2)
+    // the sums over windows of g samples (32 lanes per Stokes parameter, from wave 0 on)
     auto inc_finish = [&](int kbp) {
         const int idx = wv * 64 + lane, k = idx / kBT, tl = idx % kBT;
         if (k >= NS) return;
