@@ -338,18 +338,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(beam_waves<
         }
 
         // ---- incoherent: lane (half hb, sample tl) of wave w sums stations 8 ks + 2 w + hb; one
-        // read of a wave covers two station rows of 32 samples ----
+        // read of a wave covers two station rows of 32 samples.  For Stokes I every read is at a
+        // fixed offset from one lane base (the hi and lo words of a station row in one paired
+        // read), the padding rows (stations S .. 8 KS - 1) being zero and adding nothing ----
         if (do_inc) {
             const int tl = lane & 31, grp = 2 * wv + hb;
+            const unsigned* q = buf + grp * kBT + tl;
             float acc[NS] = {};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const int s = grp + 8 * ks;
-                if (s >= a.S) continue;
+                if (NS != 1 && s >= a.S) continue;
                 float v[2][2];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    const unsigned hw = buf[(p * kS8 + s) * kBT + tl], lw = buf[kPlaneW + (p * kS8 + s) * kBT + tl];
+                    unsigned hw, lw;
+                    if constexpr (NS == 1) {
+                        hw = q[(p * kS8 + 8 * ks) * kBT];
+                        lw = q[kPlaneW + (p * kS8 + 8 * ks) * kBT];
+                    } else {
+                        hw = buf[(p * kS8 + s) * kBT + tl];
+                        lw = buf[kPlaneW + (p * kS8 + s) * kBT + tl];
+                    }
                     // hi + lo of the (re, im) halves in one mixed-precision FMA each (exact in FP32)
                     asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(v[p][0]) : "v"(hw), "v"(lw));
                     asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(v[p][1]) : "v"(hw), "v"(lw));
