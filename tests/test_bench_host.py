@@ -78,3 +78,21 @@ def test_write_traffic_calibrates_and_flags_mixed_launches(tmp_path, monkeypatch
     assert json.loads(out.read_text()) == t
     assert bench.measured_traffic("fstage_kernel<2, 1, 64>") == 5000 * 1024
     assert bench.measured_traffic("beam_kernel<6, 1>") is None
+
+
+def test_oracle_baselines_of_the_beamformer_transform_and_gains_legs():
+    """The CPU baselines that sit beside the beamformer, output-resolution and gains legs run
+    the oracle on a bounded sample and report a positive rate in the leg's unit."""
+    from paper_1801_04834_amd import synth
+    bw = synth.Workload(name="beam_small", S=4, SB=2, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, C=256,
+                        N=256 * 32, sigma=64.0, seed=5, fp16_prescale_log2=-1)
+    beam, xf = bench.beam_cpu_baselines(bw, 5, 16, n_sub=1, n_tb=3)
+    assert beam["kind"] == xf["kind"] == "oracle"
+    assert beam["unit"] == "TeraMAC/s" and xf["unit"] == "GB/s"
+    assert beam["value"] > 0 and xf["value"] > 0 and beam["cores"] >= 1
+    assert "1 of 2 subbands" in beam["sample"] and "3 of 5 beams" in xf["sample"]
+    gw = synth.Workload(name="gains_small", S=3, SB=2, sample_type=synth.CI16, x_mode=synth.X_FP16_SPLIT, N=64 * 8,
+                        fp16_prescale_log2=-1)
+    g = bench.gains_cpu_baseline(gw)
+    assert g["kind"] == "oracle" and g["unit"] == "GB/s" and g["value"] > 0
+    assert f"({gw.SB * gw.C * 6 * 4} entries)" in g["sample"]
